@@ -1,0 +1,198 @@
+/*
+ * kiops.h - C ABI of the MI355X (gfx950) KIOPS phi-combination library.
+ *
+ * Computes, on one GPU,
+ *
+ *     w = phi_0(tau A) b_0 + tau phi_1(tau A) b_1 + ... + tau^p phi_p(tau A) b_p
+ *
+ * (Eq. (4)/(12) of Gaudreault, Rainwater & Tokman, "KIOPS: A fast adaptive
+ * Krylov subspace solver for exponential integrators", J. Comput. Phys. 372
+ * (2018)) as the first N entries of exp(tau A~) [b_0; e_p], A~ the augmented
+ * matrix of Theorem 1 (Section 3.1, Eq. (13), column order of B as in the
+ * corrigendum), by the adaptive Krylov method of Algorithm 1 with the
+ * incomplete orthogonalization procedure of Algorithm 2 (Section 3.3), the
+ * a-posteriori estimate of Eq. (36), the acceptance test of Eq. (39) and the
+ * step-size / dimension control of Algorithm 4 (Section 3.6).  The whole
+ * adaptive loop runs on the device in one persistent launch per solve.
+ *
+ * Conventions shared by every entry point:
+ *   - Data pointers named "device" are HIP device memory owned by the caller;
+ *     the library never allocates or frees device memory.
+ *   - Every function returns a kiops_status; nothing is thrown across the ABI
+ *     and the process is never terminated.
+ *   - On KIOPS_ERR_INVALID_ARG no output is modified.
+ *   - Vectors are float64, contiguous, length N (N = nx*ny*nz or nrows).
+ */
+#ifndef KIOPS_H
+#define KIOPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KIOPS_OK = 0,
+  KIOPS_ERR_INVALID_ARG = 1,     /* bad argument; outputs untouched */
+  KIOPS_ERR_OUT_OF_MEMORY = 2,   /* no workspace set, or it is too small */
+  KIOPS_ERR_DEVICE = 3,          /* a HIP call failed, or the launch could not be made co-resident */
+  KIOPS_ERR_NONFINITE = 4,       /* NaN/Inf met in a norm, an inner product or the estimate */
+  KIOPS_ERR_NOT_CONVERGED = 5,   /* substep limit reached; w holds the state at stats.t_reached */
+  KIOPS_ERR_BUDGET = 6,          /* request larger than the caller's memory budget (serving) */
+  KIOPS_ERR_UNSUPPORTED = 7      /* valid request this build does not handle */
+} kiops_status;
+
+typedef enum {
+  KIOPS_FP64 = 0,   /* basis, matrix-vector products and coefficients in float64 */
+  KIOPS_MIXED = 1   /* basis, products and coefficients in float32; inner products, norms,
+                       H, the small exponential, the error estimate, control and w in float64 */
+} kiops_precision;
+
+typedef enum {
+  KIOPS_OP_STENCIL2D_5PT = 0,   /* nz must be 1 */
+  KIOPS_OP_STENCIL3D_7PT = 1,
+  KIOPS_OP_CSR = 2
+} kiops_op_kind;
+
+/*
+ * Operator description.  A is only applied, never assembled (Section 3.3,
+ * remark after Algorithm 2).  Stencils act on a periodic nx*ny*nz box with x
+ * the fastest index (i = x + nx (y + ny z)) and spacing h:
+ *
+ *   (A u)_i = sum_d [ (kf_{i,d+} (u_{i+e_d} - u_i) - kf_{i,d-} (u_i - u_{i-e_d})) / h^2
+ *                     - adv[d] (u_{i+e_d} - u_{i-e_d}) / (2 h) ] + r_i u_i
+ *
+ * kf = diff when kappa == NULL, else the mean of the two cells' kappa.
+ * CSR: 0-based int32 row pointers (nrows+1) and column indices (nnz), float64 values.
+ * All array pointers are device memory, borrowed: they must stay valid and
+ * unchanged while the operator is used.
+ */
+typedef struct {
+  kiops_op_kind kind;
+  int64_t nx, ny, nz;
+  double h;
+  double diff;
+  const double* kappa;      /* device, N entries, or NULL */
+  double adv[3];
+  const double* reaction;   /* device, N entries, or NULL (r = 0) */
+  int64_t nrows, nnz;
+  const int32_t* rowptr;    /* device */
+  const int32_t* col;       /* device */
+  const double* val;        /* device */
+  kiops_precision precision;
+} kiops_operator_desc;
+
+/* Bounds of the Krylov dimension (Algorithm 1 inputs m_min, m_max; defaults
+ * 10 and 128, Section 3.6.2) and a cap on substeps (default 100000).  A zero
+ * field takes its default.  m_max must not exceed KIOPS_M_MAX_LIMIT. */
+typedef struct {
+  int32_t m_min;
+  int32_t m_max;
+  int32_t max_substeps;
+  int32_t reserved;
+} kiops_options;
+
+#define KIOPS_M_MAX_LIMIT 128
+#define KIOPS_P_MAX 8
+
+/* Statistics of one solve.  m_last is the dimension to use as m_init of a
+ * following, similar solve (Algorithm 1 returns it, Section 3.6). */
+typedef struct {
+  int32_t m_last;
+  int32_t substeps;       /* accepted substeps */
+  int32_t rejections;     /* rejected attempts */
+  int32_t expms;          /* small exponentials computed */
+  int32_t breakdowns;     /* happy breakdowns (Algorithm 2, line 12) */
+  int32_t grid_blocks;    /* workgroups of the persistent launch */
+  int64_t matvecs;        /* products with A~ */
+  double last_omega;      /* scaled error of the last attempt, Eq. (39) */
+  double t_reached;       /* T_now at exit (== tau on success) */
+  double alg_bytes;       /* algorithmic HBM bytes of the solve (reads + writes the method needs) */
+  double beta_last;       /* norm of the last substep's start vector */
+} kiops_stats;
+
+typedef struct kiops_operator kiops_operator;
+
+/* Validate desc and build an operator bound to hip_stream (hipStream_t, NULL
+ * = default stream).  *out is owned by the caller until kiops_destroy_operator. */
+kiops_status kiops_create_operator(const kiops_operator_desc* desc, void* hip_stream,
+                                   kiops_operator** out);
+kiops_status kiops_destroy_operator(kiops_operator* op);
+
+/* Workspace needed by kiops_phi_combination for p (0..KIOPS_P_MAX), window q
+ * (0 = full orthogonalisation, else 1..8) and options (NULL = defaults). */
+kiops_status kiops_workspace_bytes(const kiops_operator* op, int p, int q,
+                                   const kiops_options* opts, size_t* bytes);
+
+/* Attach caller-owned device memory (256-byte aligned) used by later solves.
+ * The library keeps the pointer, never frees it. */
+kiops_status kiops_set_workspace(kiops_operator* op, void* dev_ptr, size_t bytes);
+
+/*
+ * One phi-combination (the paper's Task II at a single tau):
+ *   tau   >= 0; tau == 0 copies b_0 to w with no product.
+ *   p     0..KIOPS_P_MAX; V is a host array of p+1 device pointers, V[k] = b_k.
+ *   tol   > 0, absolute tolerance of Eq. (39) (the paper's default is 1e-7).
+ *   m_init initial Krylov dimension, clamped into [m_min, m_max] (Algorithm 1, line 3).
+ *   q     IOP window: each new basis vector is orthogonalised against the last
+ *         q ones (the paper uses 2); 0 = all (full Arnoldi).
+ *   w     device, N entries, written with the result; may equal V[0], must not
+ *         overlap any other V[k].
+ *   stats may be NULL.
+ * Blocks until the result and statistics are ready.  On NONFINITE or
+ * NOT_CONVERGED, w holds the last accepted state (time stats->t_reached).
+ */
+kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const double* const* V,
+                                   double tol, int m_init, int q, const kiops_options* opts,
+                                   double* w, kiops_stats* stats);
+
+/* Human-readable name of a status code (static storage). */
+const char* kiops_status_string(kiops_status s);
+
+/* Number of compute units and the persistent grid the library would use for
+ * this operator (diagnostics). */
+kiops_status kiops_device_info(const kiops_operator* op, int* compute_units, int* grid_blocks);
+
+/*
+ * Diagnostics that run the same device code as kiops_phi_combination:
+ *
+ * kiops_iop_basis: the first substep's basis after m steps of Algorithm 2
+ *   from the start vector [b_0; mu e_p] (B scaled by nu, Eqs. (48)-(49)).
+ *   basis (device, (m+1) x (N+p) row-major, row i = v_{i+1}), H (device,
+ *   (m+1) x m row-major), *j_done = steps made (< m after a breakdown),
+ *   *beta = norm of the start vector, *nu_out = nu.
+ *
+ *   Needs the workspace of kiops_workspace_bytes(op, p, q, {m_max = m}) plus
+ *   8*N + 256 bytes (b_0 is staged there).
+ *
+ * kiops_small_expm: F = exp(tau Hs) for a device n x n row-major matrix Hs
+ *   (n <= KIOPS_M_MAX_LIMIT + 1), F device n x n, by the device's diagonal
+ *   Pade / scaling-and-squaring routine (Section 3.3.1).  scratch: device,
+ *   KIOPS_EXPM_SCRATCH_DOUBLES doubles, caller-owned.
+ */
+kiops_status kiops_iop_basis(kiops_operator* op, int p, const double* const* V, int m, int q,
+                             double* basis, double* H, int* j_done, double* beta, double* nu_out);
+#define KIOPS_EXPM_SCRATCH_DOUBLES (9 * 144 * 144)
+kiops_status kiops_small_expm(int n, const double* Hs, double tau, double* F, double* scratch,
+                              void* hip_stream);
+
+/* Host-side copy of the device step controller (Algorithm 4), for tests. */
+typedef struct {
+  double T_end, tol, T_now, tau;
+  int32_t m_min, m_max, m, have_old;
+  double tau_old, eps_old, omega_old;
+  int32_t m_old, reserved;
+} kiops_ctrl_in;
+typedef struct {
+  int32_t accept, m_new, branch, reserved;   /* branch: 0 breakdown, 1 tau_reject, 2 tau_accept, 3 m_reject, 4 m_accept, -1 non-finite */
+  double tau_new, omega;
+} kiops_ctrl_out;
+kiops_status kiops_controller_decide(const kiops_ctrl_in* in, int j, double eps, int breakdown,
+                                     kiops_ctrl_out* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KIOPS_H */

@@ -1,0 +1,214 @@
+"""MI355X (gfx950) KIOPS phi-combination library: Python binding.
+
+    w = phi_0(tau A) b_0 + tau phi_1(tau A) b_1 + ... + tau^p phi_p(tau A) b_p
+
+(Gaudreault, Rainwater & Tokman, J. Comput. Phys. 372 (2018), Eq. (4)),
+computed by the device-resident adaptive Krylov/IOP solver in ``libkiops.so``.
+PyTorch supplies device memory and the stream; this module only marshals
+arguments into the C ABI of ``include/kiops.h``.  There is no CPU fallback:
+without the built library or a GPU every entry point raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence
+
+from . import _lib
+from ._lib import KiopsError  # noqa: F401
+
+__all__ = ["Operator", "phi_combination", "iop_basis", "small_expm", "controller_decide",
+           "KiopsError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _require_cuda_f64(t, n: Optional[int], name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries")
+
+
+class Operator:
+    """A stencil or CSR operator bound to a stream, with its workspace.
+
+    Coefficient tensors are borrowed: keep them alive and unchanged while the
+    operator is used (the Operator keeps references)."""
+
+    def __init__(self, kind: str, *, nx: int = 0, ny: int = 0, nz: int = 1, h: float = 1.0,
+                 diff: float = 0.0, kappa=None, adv=(0.0, 0.0, 0.0), reaction=None,
+                 rowptr=None, col=None, val=None, precision: str = "fp64", stream=None):
+        torch = _torch()
+        lib = _lib.load()
+        d = _lib.OperatorDesc()
+        kinds = {"stencil2d": _lib.OP_STENCIL2D_5PT, "stencil3d": _lib.OP_STENCIL3D_7PT,
+                 "csr": _lib.OP_CSR}
+        if kind not in kinds:
+            raise ValueError(f"unknown operator kind {kind}")
+        d.kind = kinds[kind]
+        d.precision = {"fp64": _lib.FP64, "mixed": _lib.MIXED}[precision]
+        self._keep = []
+        if kind == "csr":
+            n = int(rowptr.numel()) - 1
+            for t, nm, dt in ((rowptr, "rowptr", torch.int32), (col, "col", torch.int32),
+                              (val, "val", torch.float64)):
+                if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                    raise TypeError(f"{nm} must be a contiguous device tensor of {dt}")
+            d.nrows, d.nnz = n, int(col.numel())
+            d.rowptr, d.col, d.val = _ptr(rowptr), _ptr(col), _ptr(val)
+            self._keep += [rowptr, col, val]
+            self.n = n
+        else:
+            d.nx, d.ny, d.nz, d.h, d.diff = int(nx), int(ny), int(nz), float(h), float(diff)
+            d.adv[0], d.adv[1], d.adv[2] = (float(a) for a in adv)
+            self.n = int(nx) * int(ny) * int(nz)
+            if kappa is not None:
+                _require_cuda_f64(kappa, self.n, "kappa")
+                d.kappa = _ptr(kappa)
+                self._keep.append(kappa)
+            if reaction is not None:
+                _require_cuda_f64(reaction, self.n, "reaction")
+                d.reaction = _ptr(reaction)
+                self._keep.append(reaction)
+        self.kind = kind
+        self.precision = precision
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._desc = d
+        handle = C.c_void_p()
+        _lib.check(lib.kiops_create_operator(C.byref(d), C.c_void_p(self.stream.cuda_stream),
+                                             C.byref(handle)), "kiops_create_operator")
+        self._h = handle
+        self._ws = None
+        self._lib = lib
+
+    @classmethod
+    def from_desc(cls, desc, device="cuda", precision: Optional[str] = None, stream=None):
+        """Build from a workloads.StencilDesc / CsrDesc (numpy data copied to the device)."""
+        torch = _torch()
+        prec = precision or "fp64"
+        if getattr(desc, "kind", None) == "csr":
+            return cls("csr", rowptr=torch.as_tensor(desc.rowptr, dtype=torch.int32, device=device),
+                       col=torch.as_tensor(desc.col, dtype=torch.int32, device=device),
+                       val=torch.as_tensor(desc.val, dtype=torch.float64, device=device),
+                       precision=prec, stream=stream)
+        f = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float64, device=device)  # noqa: E731
+        return cls(desc.kind, nx=desc.nx, ny=desc.ny, nz=desc.nz, h=desc.h, diff=desc.diff,
+                   kappa=f(desc.kappa), adv=desc.adv, reaction=f(desc.reaction),
+                   precision=prec, stream=stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.kiops_destroy_operator(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def device_info(self):
+        cu, g = C.c_int(), C.c_int()
+        _lib.check(self._lib.kiops_device_info(self._h, C.byref(cu), C.byref(g)), "kiops_device_info")
+        return cu.value, g.value
+
+    def workspace_bytes(self, p: int, q: int = 2, m_min: int = 0, m_max: int = 0,
+                        max_substeps: int = 0) -> int:
+        o = _lib.Options(m_min, m_max, max_substeps, 0)
+        out = C.c_size_t()
+        _lib.check(self._lib.kiops_workspace_bytes(self._h, p, q, C.byref(o), C.byref(out)),
+                   "kiops_workspace_bytes")
+        return out.value
+
+    def ensure_workspace(self, nbytes: int):
+        torch = _torch()
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = _ptr(self._ws)
+        aligned = (base + 255) // 256 * 256
+        _lib.check(self._lib.kiops_set_workspace(self._h, C.c_void_p(aligned),
+                                                 self._ws.numel() - (aligned - base)),
+                   "kiops_set_workspace")
+
+
+def _vec_ptrs(vectors: Sequence, n: int):
+    arr = (C.c_void_p * len(vectors))()
+    for k, v in enumerate(vectors):
+        _require_cuda_f64(v, n, f"V[{k}]")
+        arr[k] = _ptr(v)
+    return arr
+
+
+def phi_combination(op: Operator, tau: float, vectors: Sequence, tol: float = 1e-8,
+                    m_init: int = 10, q: int = 2, m_min: int = 0, m_max: int = 0,
+                    max_substeps: int = 0, out=None, check: bool = True):
+    """w = sum_k tau^k phi_k(tau A) vectors[k]; returns (w, stats dict, status)."""
+    torch = _torch()
+    p = len(vectors) - 1
+    V = _vec_ptrs(vectors, op.n)
+    w = out if out is not None else torch.empty(op.n, dtype=torch.float64, device="cuda")
+    _require_cuda_f64(w, op.n, "w")
+    op.ensure_workspace(op.workspace_bytes(p, q, m_min, m_max, max_substeps))
+    o = _lib.Options(m_min, m_max, max_substeps, 0)
+    st = _lib.Stats()
+    status = op._lib.kiops_phi_combination(op._h, float(tau), p, V, float(tol), int(m_init), int(q),
+                                           C.byref(o), C.c_void_p(_ptr(w)), C.byref(st))
+    if check:
+        _lib.check(status, "kiops_phi_combination")
+    return w, st.as_dict(), status
+
+
+def iop_basis(op: Operator, vectors: Sequence, m: int, q: int = 2):
+    """First-substep basis and H after m steps of Algorithm 2 (diagnostics).
+    Returns (basis (j+1, N+p) or (j, N+p) after breakdown, H (m+1, m), j, beta, nu)."""
+    torch = _torch()
+    p = len(vectors) - 1
+    V = _vec_ptrs(vectors, op.n)
+    need = op.workspace_bytes(p, q, m_min=1, m_max=m) + 8 * op.n + 256
+    op.ensure_workspace(need)
+    basis = torch.zeros((m + 1, op.n + p), dtype=torch.float64, device="cuda")
+    H = torch.zeros((m + 1, m), dtype=torch.float64, device="cuda")
+    j, beta, nu = C.c_int(), C.c_double(), C.c_double()
+    _lib.check(op._lib.kiops_iop_basis(op._h, p, V, m, q, C.c_void_p(_ptr(basis)), C.c_void_p(_ptr(H)),
+                                       C.byref(j), C.byref(beta), C.byref(nu)), "kiops_iop_basis")
+    return basis, H, j.value, beta.value, nu.value
+
+
+def small_expm(Hs, tau: float, stream=None):
+    """exp(tau Hs) for a device (n, n) float64 matrix by the device routine."""
+    torch = _torch()
+    lib = _lib.load()
+    n = int(Hs.shape[0])
+    Hs = Hs.contiguous()
+    _require_cuda_f64(Hs, n * n, "Hs")
+    F = torch.empty_like(Hs)
+    scratch = torch.empty(_lib.EXPM_SCRATCH_DOUBLES, dtype=torch.float64, device="cuda")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _lib.check(lib.kiops_small_expm(n, C.c_void_p(_ptr(Hs)), float(tau), C.c_void_p(_ptr(F)),
+                                    C.c_void_p(_ptr(scratch)), C.c_void_p(s.cuda_stream)),
+               "kiops_small_expm")
+    return F
+
+
+def controller_decide(state: dict, j: int, eps: float, breakdown: bool) -> dict:
+    """One decision of the device controller (host copy of the same code)."""
+    lib = _lib.load()
+    ci = _lib.CtrlIn()
+    for k, v in state.items():
+        setattr(ci, k, v)
+    co = _lib.CtrlOut()
+    _lib.check(lib.kiops_controller_decide(C.byref(ci), int(j), float(eps), int(bool(breakdown)),
+                                           C.byref(co)), "kiops_controller_decide")
+    return {"accept": bool(co.accept), "m_new": co.m_new, "branch": _lib.BRANCH_NAMES[co.branch],
+            "tau_new": co.tau_new, "omega": co.omega}

@@ -1,0 +1,481 @@
+// Host side of the C ABI declared in include/kiops.h: argument checks,
+// workspace layout, the cooperative launch of the persistent solve kernel,
+// and the diagnostics entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "../../include/kiops.h"
+#include "controller.h"
+#include "op_stencil2d.h"
+#include "solver_kernel.h"
+
+using namespace kiops;
+
+struct kiops_operator {
+  kiops_operator_desc d;
+  hipStream_t stream;
+  int device;
+  int cus;
+  uint64_t clock_hz;
+  int64_t N;
+  void* ws;
+  size_t ws_bytes;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t ctrl, bar, H, G, Y, sinv, unorm, partials, expm, trace, slots, bcopy, coef, total;
+  int nwg, ndot_stride;
+};
+
+int elem_size(const kiops_operator* op) { return op->d.precision == KIOPS_MIXED ? 4 : 8; }
+
+int coef_streams(const kiops_operator* op) {
+  int c = 0;
+  if (op->d.reaction) ++c;
+  if (op->d.kappa) ++c;
+  return c;
+}
+
+// The kernel instantiation that serves an operator.
+const void* kernel_for(const kiops_operator* op) {
+  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
+    if (op->d.precision == KIOPS_MIXED) return (const void*)kiops_solve_kernel<Stencil2D<float>, float>;
+    return (const void*)kiops_solve_kernel<Stencil2D<double>, double>;
+  }
+  return nullptr;
+}
+
+int64_t work_tiles(const kiops_operator* op) {
+  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
+    const int64_t tx = (op->d.nx + Stencil2D<double>::TX - 1) / Stencil2D<double>::TX;
+    const int64_t ty = (op->d.ny + Stencil2D<double>::TY - 1) / Stencil2D<double>::TY;
+    return tx * ty;
+  }
+  return 1;
+}
+
+// Persistent grid: all workgroups co-resident, no more than the tiles of work.
+kiops_status grid_size(const kiops_operator* op, int* nwg) {
+  const void* fn = kernel_for(op);
+  if (!fn) return KIOPS_ERR_UNSUPPORTED;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess || per_cu < 1)
+    return KIOPS_ERR_DEVICE;
+  int64_t g = (int64_t)per_cu * op->cus;
+  g = std::min<int64_t>(g, std::max<int64_t>(1, work_tiles(op)));
+  *nwg = (int)g;
+  return KIOPS_OK;
+}
+
+void resolve_options(const kiops_options* o, int* m_min, int* m_max, int* max_sub) {
+  *m_min = (o && o->m_min > 0) ? o->m_min : 10;
+  *m_max = (o && o->m_max > 0) ? o->m_max : 128;
+  *max_sub = (o && o->max_substeps > 0) ? o->max_substeps : 100000;
+}
+
+Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
+  L.nwg = nwg;
+  L.ndot_stride = std::max(kPM, kDotSlots);
+  (void)q;
+  L.ctrl = take(sizeof(Ctrl));
+  L.bar = take(sizeof(Barrier));
+  L.H = take(sizeof(double) * kLdh * kLdh);
+  L.G = take(sizeof(double) * kLdh * kLdh);
+  L.Y = take(sizeof(double) * kLdh * kPM);
+  L.sinv = take(sizeof(double) * kLdh);
+  L.unorm = take(sizeof(double) * kLdh);
+  L.partials = take(sizeof(double) * (size_t)nwg * L.ndot_stride);
+  L.expm = take(sizeof(double) * (size_t)kExpmSlots * kExpmSlot);
+  L.trace = take(sizeof(double) * (size_t)kTraceMax * kTraceStride);
+  const size_t es = (size_t)elem_size(op);
+  L.slots = take(es * (size_t)(m_max + 1) * (size_t)op->N);
+  L.bcopy = take(op->d.precision == KIOPS_MIXED ? es * (size_t)p * op->N : 0);
+  L.coef = take(op->d.precision == KIOPS_MIXED ? es * (size_t)coef_streams(op) * op->N : 0);
+  L.total = off;
+  return L;
+}
+
+bool hip_ok(hipError_t e) { return e == hipSuccess; }
+
+template <typename T>
+Stencil2D<T> make_stencil2d(const kiops_operator* op, int p, const double* const* V, char* ws,
+                            const Layout& L) {
+  const auto& d = op->d;
+  Stencil2D<T> s{};
+  s.N = op->N;
+  s.nx = (int)d.nx;
+  s.ny = (int)d.ny;
+  s.tiles_x = (int)((d.nx + Stencil2D<T>::TX - 1) / Stencil2D<T>::TX);
+  const int tiles_y = (int)((d.ny + Stencil2D<T>::TY - 1) / Stencil2D<T>::TY);
+  s.ntiles = s.tiles_x * tiles_y;
+  const double cD = d.diff / (d.h * d.h);
+  const double cx = d.adv[0] / (2.0 * d.h);
+  const double cy = d.adv[1] / (2.0 * d.h);
+  s.wE = (T)(cD - cx);
+  s.wW = (T)(cD + cx);
+  s.wN = (T)(cD - cy);
+  s.wS = (T)(cD + cy);
+  s.wC = (T)(-4.0 * cD);
+  s.p = p;
+  const bool mixed = d.precision == KIOPS_MIXED;
+  for (int c = 0; c < kPM; ++c) s.B[c] = nullptr;
+  if (mixed) {
+    T* bc = reinterpret_cast<T*>(ws + L.bcopy);
+    for (int c = 0; c < p; ++c) s.B[c] = bc + (size_t)c * op->N;
+    s.r_src = d.reaction;
+    s.r_dst = d.reaction ? reinterpret_cast<T*>(ws + L.coef) : nullptr;
+    s.r = s.r_dst;
+  } else {
+    for (int c = 0; c < p; ++c) s.B[c] = reinterpret_cast<const T*>(V[p - c]);
+    s.r = reinterpret_cast<const T*>(d.reaction);
+    s.r_src = nullptr;
+    s.r_dst = nullptr;
+  }
+  return s;
+}
+
+KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double tau, int p,
+                    const double* const* V, double tol, int m_init, int q, int m_min, int m_max,
+                    int max_sub, int mode, double* w) {
+  KParams P{};
+  P.N = op->N;
+  P.p = p;
+  P.q = q;
+  P.m_min = m_min;
+  P.m_max = m_max;
+  P.m_init = m_init;
+  P.max_substeps = max_sub;
+  P.mode = mode;
+  P.mixed = op->d.precision == KIOPS_MIXED;
+  P.nwg = L.nwg;
+  P.ndot_stride = L.ndot_stride;
+  P.T_end = tau;
+  P.tol = tol;
+  P.elem_bytes = (double)elem_size(op);
+  P.coef_streams = (double)coef_streams(op);
+  P.spin_limit = op->clock_hz * 60ull;   // a minute without progress aborts the solve
+  for (int k = 0; k <= kPM; ++k) P.b[k] = (k <= p) ? V[k] : nullptr;
+  P.w = w;
+  P.slots = ws + L.slots;
+  P.bcopy = ws + L.bcopy;
+  P.ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
+  P.bar = reinterpret_cast<Barrier*>(ws + L.bar);
+  P.H = reinterpret_cast<double*>(ws + L.H);
+  P.G = reinterpret_cast<double*>(ws + L.G);
+  P.Y = reinterpret_cast<double*>(ws + L.Y);
+  P.sinv = reinterpret_cast<double*>(ws + L.sinv);
+  P.unorm = reinterpret_cast<double*>(ws + L.unorm);
+  P.partials = reinterpret_cast<double*>(ws + L.partials);
+  P.expm = reinterpret_cast<double*>(ws + L.expm);
+  P.trace = reinterpret_cast<double*>(ws + L.trace);
+  return P;
+}
+
+// Launch one persistent solve and wait for its control block.
+kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, const double* const* V,
+                       Ctrl* host_ctrl, unsigned* host_abort) {
+  char* ws = reinterpret_cast<char*>(op->ws);
+  hipLaunchKernelGGL(kiops_reset_kernel, dim3(1), dim3(64), 0, op->stream, P.bar, P.ctrl);
+  if (!hip_ok(hipGetLastError())) return KIOPS_ERR_DEVICE;
+  hipError_t e = hipSuccess;
+  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
+    if (op->d.precision == KIOPS_MIXED) {
+      auto s = make_stencil2d<float>(op, p, V, ws, L);
+      void* args[] = {&P, &s};
+      e = hipLaunchCooperativeKernel((const void*)kiops_solve_kernel<Stencil2D<float>, float>,
+                                     dim3(L.nwg), dim3(kThreads), args, 0, op->stream);
+    } else {
+      auto s = make_stencil2d<double>(op, p, V, ws, L);
+      void* args[] = {&P, &s};
+      e = hipLaunchCooperativeKernel((const void*)kiops_solve_kernel<Stencil2D<double>, double>,
+                                     dim3(L.nwg), dim3(kThreads), args, 0, op->stream);
+    }
+  } else {
+    return KIOPS_ERR_UNSUPPORTED;
+  }
+  if (!hip_ok(e)) return KIOPS_ERR_DEVICE;
+  Barrier hb{};
+  if (!hip_ok(hipMemcpyAsync(host_ctrl, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, op->stream)))
+    return KIOPS_ERR_DEVICE;
+  if (!hip_ok(hipMemcpyAsync(&hb, P.bar, sizeof(Barrier), hipMemcpyDeviceToHost, op->stream)))
+    return KIOPS_ERR_DEVICE;
+  if (!hip_ok(hipStreamSynchronize(op->stream))) return KIOPS_ERR_DEVICE;
+  *host_abort = hb.abort;
+  return KIOPS_OK;
+}
+
+void fill_stats(const Ctrl& c, int nwg, kiops_stats* st) {
+  if (!st) return;
+  st->m_last = c.m;
+  st->substeps = c.substeps;
+  st->rejections = c.rejections;
+  st->expms = c.expms;
+  st->breakdowns = c.breakdowns;
+  st->grid_blocks = nwg;
+  st->matvecs = c.matvecs;
+  st->last_omega = c.last_omega;
+  st->t_reached = c.T_now;
+  st->alg_bytes = c.alg_bytes;
+  st->beta_last = c.beta;
+}
+
+kiops_status check_vectors(const kiops_operator* op, int p, const double* const* V, const double* w) {
+  if (!V || !w || p < 0 || p > KIOPS_P_MAX) return KIOPS_ERR_INVALID_ARG;
+  const size_t bytes = sizeof(double) * (size_t)op->N;
+  for (int k = 0; k <= p; ++k) {
+    if (!V[k]) return KIOPS_ERR_INVALID_ARG;
+    if (k > 0) {
+      const char* a = reinterpret_cast<const char*>(V[k]);
+      const char* b = reinterpret_cast<const char*>(w);
+      if (a < b + bytes && b < a + bytes) return KIOPS_ERR_INVALID_ARG;   // w overlaps b_k, k >= 1
+    }
+  }
+  return KIOPS_OK;
+}
+
+__global__ void export_basis_kernel(const void* slots, const double* w, int mixed, int64_t N, int p,
+                                    int nvec, const double* sinv, const double* Y, double* out) {
+  const int64_t stride = N + p;
+  const int64_t total = (int64_t)nvec * stride;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / stride) + 1;       // basis index, 1-based
+    const int64_t n = e % stride;
+    double v;
+    if (n < N) {
+      if (i == 1 && !mixed) v = w[n];
+      else if (mixed) v = (double)reinterpret_cast<const float*>(slots)[(int64_t)(i - 1) * N + n];
+      else v = reinterpret_cast<const double*>(slots)[(int64_t)(i - 1) * N + n];
+    } else {
+      v = Y[i * kPM + (n - N)];
+    }
+    out[e] = v * sinv[i];
+  }
+}
+
+__global__ void export_h_kernel(const double* H, int m, double* out) {
+  for (int e = threadIdx.x; e < (m + 1) * m; e += blockDim.x) {
+    const int r = e / m, c = e % m;
+    out[e] = H[(r + 1) * kLdh + (c + 1)];
+  }
+}
+
+__global__ void small_expm_kernel(const double* Hs, int n, double tau, double* F, double* scratch) {
+  __shared__ double lds[kLdsDoubles];
+  const int n16 = pad16(n);
+  for (int e = threadIdx.x; e < n16 * n16; e += kThreads) {
+    const int r = e / n16, c = e % n16;
+    scratch[r * kExpmLd + c] = (r < n && c < n) ? tau * Hs[r * n + c] : 0.0;
+  }
+  __syncthreads();
+  const int slot = wg_expm(scratch, n, lds);
+  const double* R = scratch + (size_t)slot * kExpmSlot;
+  for (int e = threadIdx.x; e < n * n; e += kThreads) F[e] = R[(e / n) * kExpmLd + (e % n)];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kiops_status_string(kiops_status s) {
+  switch (s) {
+    case KIOPS_OK: return "ok";
+    case KIOPS_ERR_INVALID_ARG: return "invalid argument";
+    case KIOPS_ERR_OUT_OF_MEMORY: return "workspace missing or too small";
+    case KIOPS_ERR_DEVICE: return "device error";
+    case KIOPS_ERR_NONFINITE: return "non-finite value";
+    case KIOPS_ERR_NOT_CONVERGED: return "substep limit reached";
+    case KIOPS_ERR_BUDGET: return "over memory budget";
+    case KIOPS_ERR_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+kiops_status kiops_create_operator(const kiops_operator_desc* desc, void* hip_stream, kiops_operator** out) {
+  if (!desc || !out) return KIOPS_ERR_INVALID_ARG;
+  const kiops_operator_desc& d = *desc;
+  int64_t N = 0;
+  if (d.precision != KIOPS_FP64 && d.precision != KIOPS_MIXED) return KIOPS_ERR_INVALID_ARG;
+  if (d.kind == KIOPS_OP_STENCIL2D_5PT || d.kind == KIOPS_OP_STENCIL3D_7PT) {
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1 || !(d.h > 0.0) || !std::isfinite(d.h)) return KIOPS_ERR_INVALID_ARG;
+    if (d.kind == KIOPS_OP_STENCIL2D_5PT && d.nz != 1) return KIOPS_ERR_INVALID_ARG;
+    if (d.nx > (1 << 30) || d.ny > (1 << 30) || d.nz > (1 << 30)) return KIOPS_ERR_INVALID_ARG;
+    N = d.nx * d.ny * d.nz;
+    if (!std::isfinite(d.diff) || !std::isfinite(d.adv[0]) || !std::isfinite(d.adv[1]) ||
+        !std::isfinite(d.adv[2]))
+      return KIOPS_ERR_INVALID_ARG;
+  } else if (d.kind == KIOPS_OP_CSR) {
+    if (d.nrows < 1 || d.nnz < 0 || !d.rowptr || !d.col || (!d.val && d.nnz > 0)) return KIOPS_ERR_INVALID_ARG;
+    N = d.nrows;
+  } else {
+    return KIOPS_ERR_INVALID_ARG;
+  }
+  if (N > ((int64_t)1 << 34)) return KIOPS_ERR_INVALID_ARG;
+  kiops_operator* op = new (std::nothrow) kiops_operator();
+  if (!op) return KIOPS_ERR_OUT_OF_MEMORY;
+  op->d = d;
+  op->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  op->N = N;
+  op->ws = nullptr;
+  op->ws_bytes = 0;
+  if (!hip_ok(hipGetDevice(&op->device))) { delete op; return KIOPS_ERR_DEVICE; }
+  if (!hip_ok(hipDeviceGetAttribute(&op->cus, hipDeviceAttributeMultiprocessorCount, op->device))) {
+    delete op;
+    return KIOPS_ERR_DEVICE;
+  }
+  int khz = 0;
+  if (!hip_ok(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, op->device)) || khz <= 0)
+    khz = 100000;
+  op->clock_hz = (uint64_t)khz * 1000ull;
+  *out = op;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_destroy_operator(kiops_operator* op) {
+  if (!op) return KIOPS_ERR_INVALID_ARG;
+  delete op;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_device_info(const kiops_operator* op, int* compute_units, int* grid_blocks) {
+  if (!op) return KIOPS_ERR_INVALID_ARG;
+  if (compute_units) *compute_units = op->cus;
+  if (grid_blocks) {
+    int g = 0;
+    kiops_status s = grid_size(op, &g);
+    if (s != KIOPS_OK) return s;
+    *grid_blocks = g;
+  }
+  return KIOPS_OK;
+}
+
+kiops_status kiops_workspace_bytes(const kiops_operator* op, int p, int q, const kiops_options* opts,
+                                   size_t* bytes) {
+  if (!op || !bytes || p < 0 || p > KIOPS_P_MAX || q < 0 || q > 8) return KIOPS_ERR_INVALID_ARG;
+  int m_min, m_max, max_sub;
+  resolve_options(opts, &m_min, &m_max, &max_sub);
+  if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max) return KIOPS_ERR_INVALID_ARG;
+  int nwg = 0;
+  kiops_status s = grid_size(op, &nwg);
+  if (s != KIOPS_OK) return s;
+  *bytes = make_layout(op, p, q, m_max, nwg).total;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_set_workspace(kiops_operator* op, void* dev_ptr, size_t bytes) {
+  if (!op || (!dev_ptr && bytes > 0)) return KIOPS_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign != 0) return KIOPS_ERR_INVALID_ARG;
+  op->ws = dev_ptr;
+  op->ws_bytes = bytes;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const double* const* V,
+                                   double tol, int m_init, int q, const kiops_options* opts,
+                                   double* w, kiops_stats* stats) {
+  if (!op) return KIOPS_ERR_INVALID_ARG;
+  if (!(tau >= 0.0) || !std::isfinite(tau) || !(tol > 0.0) || !std::isfinite(tol) || m_init < 1 ||
+      q < 0 || q > 8)
+    return KIOPS_ERR_INVALID_ARG;
+  kiops_status s = check_vectors(op, p, V, w);
+  if (s != KIOPS_OK) return s;
+  int m_min, m_max, max_sub;
+  resolve_options(opts, &m_min, &m_max, &max_sub);
+  if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max || m_min < 1) return KIOPS_ERR_INVALID_ARG;
+  if (q == 0 || q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
+  if (op->d.kind != KIOPS_OP_STENCIL2D_5PT || op->d.kappa) return KIOPS_ERR_UNSUPPORTED;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (tau == 0.0) {
+    if (w != V[0] &&
+        !hip_ok(hipMemcpyAsync(w, V[0], sizeof(double) * op->N, hipMemcpyDeviceToDevice, op->stream)))
+      return KIOPS_ERR_DEVICE;
+    if (!hip_ok(hipStreamSynchronize(op->stream))) return KIOPS_ERR_DEVICE;
+    return KIOPS_OK;
+  }
+  int nwg = 0;
+  s = grid_size(op, &nwg);
+  if (s != KIOPS_OK) return s;
+  const Layout L = make_layout(op, p, q, m_max, nwg);
+  if (!op->ws || op->ws_bytes < L.total) return KIOPS_ERR_OUT_OF_MEMORY;
+  KParams P = make_params(op, L, reinterpret_cast<char*>(op->ws), tau, p, V, tol, m_init, q, m_min, m_max,
+                          max_sub, kModeSolve, w);
+  Ctrl hc{};
+  unsigned abort_flag = 0;
+  s = run_solve(op, L, P, p, V, &hc, &abort_flag);
+  if (s != KIOPS_OK) return s;
+  fill_stats(hc, nwg, stats);
+  if (abort_flag) return KIOPS_ERR_DEVICE;
+  return (kiops_status)hc.status;
+}
+
+kiops_status kiops_iop_basis(kiops_operator* op, int p, const double* const* V, int m, int q,
+                             double* basis, double* H, int* j_done, double* beta, double* nu_out) {
+  if (!op || !basis || !H || m < 1 || m > KIOPS_M_MAX_LIMIT || q < 1 || q > kWinMax)
+    return KIOPS_ERR_INVALID_ARG;
+  if (!V || p < 0 || p > KIOPS_P_MAX) return KIOPS_ERR_INVALID_ARG;
+  for (int k = 0; k <= p; ++k)
+    if (!V[k]) return KIOPS_ERR_INVALID_ARG;
+  if (op->d.kind != KIOPS_OP_STENCIL2D_5PT || op->d.kappa) return KIOPS_ERR_UNSUPPORTED;
+  int nwg = 0;
+  kiops_status s = grid_size(op, &nwg);
+  if (s != KIOPS_OK) return s;
+  const Layout L = make_layout(op, p, q, m, nwg);
+  // w holds b_0 during the run: place it in the last slot row of the workspace tail
+  const size_t need = L.total + align_up(sizeof(double) * (size_t)op->N);
+  if (!op->ws || op->ws_bytes < need) return KIOPS_ERR_OUT_OF_MEMORY;
+  char* ws = reinterpret_cast<char*>(op->ws);
+  double* wtmp = reinterpret_cast<double*>(ws + L.total);
+  KParams P = make_params(op, L, ws, 1.0, p, V, 1.0, m, q, 1, m, 1, kModeBasis, wtmp);
+  Ctrl hc{};
+  unsigned abort_flag = 0;
+  s = run_solve(op, L, P, p, V, &hc, &abort_flag);
+  if (s != KIOPS_OK) return s;
+  if (abort_flag) return KIOPS_ERR_DEVICE;
+  if (hc.status != KIOPS_OK) return (kiops_status)hc.status;
+  const int jd = hc.breakdown ? (hc.kp - 1) : m;
+  const int nvec = hc.breakdown ? jd : jd + 1;
+  hipLaunchKernelGGL(export_basis_kernel, dim3(1024), dim3(256), 0, op->stream, P.slots, wtmp, P.mixed,
+                     op->N, p, nvec, P.sinv, P.Y, basis);
+  hipLaunchKernelGGL(export_h_kernel, dim3(1), dim3(256), 0, op->stream, P.H, m, H);
+  if (!hip_ok(hipGetLastError()) || !hip_ok(hipStreamSynchronize(op->stream))) return KIOPS_ERR_DEVICE;
+  if (j_done) *j_done = jd;
+  if (beta) *beta = hc.beta;
+  if (nu_out) *nu_out = hc.nu;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_small_expm(int n, const double* Hs, double tau, double* F, double* scratch,
+                              void* hip_stream) {
+  if (n < 1 || n > kExpmMaxN || !Hs || !F || !scratch || !std::isfinite(tau)) return KIOPS_ERR_INVALID_ARG;
+  static_assert(KIOPS_EXPM_SCRATCH_DOUBLES == kExpmSlots * kExpmSlot, "expm scratch size");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(small_expm_kernel, dim3(1), dim3(kThreads), 0, st, Hs, n, tau, F, scratch);
+  if (!hip_ok(hipGetLastError()) || !hip_ok(hipStreamSynchronize(st))) return KIOPS_ERR_DEVICE;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_controller_decide(const kiops_ctrl_in* in, int j, double eps, int breakdown,
+                                     kiops_ctrl_out* out) {
+  if (!in || !out) return KIOPS_ERR_INVALID_ARG;
+  CtrlIn ci;
+  static_assert(sizeof(CtrlIn) == sizeof(kiops_ctrl_in), "controller input layout");
+  static_assert(sizeof(CtrlOut) == sizeof(kiops_ctrl_out), "controller output layout");
+  std::memcpy(&ci, in, sizeof(ci));
+  const CtrlOut o = ctrl_decide(ci, j, eps, breakdown != 0);
+  std::memcpy(out, &o, sizeof(o));
+  return KIOPS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Device-side state shared by the persistent KIOPS solver kernels.
+//
+// One solve is one cooperative launch.  Every workgroup runs the same loop of
+// phases separated by grid-wide barriers; the last workgroup to reach a
+// barrier runs a serial "epilogue" (reductions, the Hessenberg bookkeeping of
+// Algorithm 2, the small exponential of Section 3.3.1, the controller of
+// Algorithm 4) before releasing the others.  The host sees the solve only at
+// launch and at completion.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kiops.h"
+
+namespace kiops {
+
+constexpr int kThreads = 256;
+constexpr int kMaxBasis = KIOPS_M_MAX_LIMIT + 1;   // v_1 .. v_{m_max+1}
+constexpr int kLdh = kMaxBasis + 2;                 // H, G indexed 1-based
+constexpr int kPM = KIOPS_P_MAX;
+constexpr int kWinMax = 4;                          // windows q <= 4 use register accumulators
+constexpr int kTraceMax = 4096;
+constexpr int kTraceStride = 6;
+
+enum Phase : int32_t { kPhasePass = 0, kPhaseGather = 1, kPhaseDone = 2 };
+enum Mode : int32_t { kModeSolve = 0, kModeBasis = 1 };
+
+// Small solver state, in the workspace.  Written only inside epilogues.
+struct Ctrl {
+  // ---- what the workgroups do next
+  int32_t phase;
+  int32_t kp;        // next pass produces basis vector R_kp (1-based)
+  int32_t flo;       // formation window: R_i, i in [flo, kp-1] (kp >= 2)
+  int32_t dlo;       // inner products of the pass: i in [dlo, kp]
+  int32_t jg;        // gather: number of basis vectors
+  int32_t status;
+  int32_t mode;
+  int32_t pad0;
+  double a;                    // R_kp = a U_{kp-1} + sum_i bw[i] R_i
+  double bw[kLdh];
+  double yb_prev[kPM];         // nu * y(R_{kp-1}): B term of U_{kp-1}
+  double yb_cur[kPM];          // nu * y(R_kp):     B term of U_kp
+  double cg[kLdh];             // gather coefficients
+  // ---- solver state (Algorithm 1)
+  double T_now, T_end, tau, tol, beta, nu, mu;
+  double tau_new;              // decided at acceptance, applied after the gather
+  int32_t m, m_new, p, q, m_min, m_max, max_substeps, breakdown;
+  int32_t have_old, m_old;
+  double tau_old, eps_old, omega_old;
+  // ---- statistics
+  int32_t substeps, rejections, expms, breakdowns, attempts, pad1;
+  int64_t matvecs;
+  double last_omega, alg_bytes;
+  double s_last;
+};
+
+struct Barrier {
+  unsigned count;
+  unsigned gen;
+  unsigned abort;
+  unsigned pad;
+};
+
+// Kernel parameters common to all operators (passed by value).
+struct KParams {
+  int64_t N;
+  int p, q, m_min, m_max, m_init, max_substeps;
+  int mode, mixed, nwg, ndot_stride;
+  double T_end, tol;
+  double elem_bytes;           // bytes per basis element (8 or 4)
+  double coef_streams;         // per-cell coefficient arrays the operator reads
+  uint64_t spin_limit;         // wall-clock ticks a barrier may wait before aborting
+  const double* b[kPM + 1];    // caller's b_0..b_p
+  double* w;                   // result (FP64), also R_1 in FP64 mode
+  void* slots;                 // basis vector storage, slot i at (i-1)*N elements
+  void* bcopy;                 // mixed: float copies of B columns
+  Ctrl* ctrl;
+  Barrier* bar;
+  double* H;                   // kLdh x kLdh
+  double* G;                   // Gram matrix of the normalised basis, kLdh x kLdh
+  double* Y;                   // trailing (y) parts of R_i, kLdh x kPM
+  double* sinv;                // v_i = R_i * sinv[i]
+  double* unorm;               // ||A~ v_i||
+  double* partials;            // nwg x ndot_stride
+  double* expm;                // small-exponential scratch
+  double* trace;               // kTraceMax x kTraceStride
+};
+
+}  // namespace kiops
