@@ -111,6 +111,14 @@ typedef struct {
   double t_reached;       /* T_now at exit (== tau on success) */
   double alg_bytes;       /* algorithmic HBM bytes of the solve (reads + writes the method needs) */
   double beta_last;       /* norm of the last substep's start vector */
+  double time_work_s;     /* workgroup 0: time in its own share of the passes and gathers */
+  double time_wait_s;     /* workgroup 0: time waiting for the other workgroups at barriers */
+  double time_epilogue_s; /* serial epilogues: reductions, small exponential, controller */
+  double time_expm_s;     /* part of time_epilogue_s spent in small exponentials */
+  /* With the environment variable KIOPS_PROFILE=1: sums over barriers of the
+   * latest and of the mean workgroup arrival after the previous release. */
+  double arrive_max_s, arrive_mean_s;
+  int64_t barriers;
 } kiops_stats;
 
 typedef struct kiops_operator kiops_operator;

@@ -30,7 +30,11 @@ from .expm import expm
 
 def phi_combination_arnoldi(apply_A: Callable[[np.ndarray], np.ndarray], T: float,
                             vectors: Sequence[np.ndarray], tol_o: float = 1e-12,
-                            m: int = 48, max_substeps: int = 100000, stats: dict = None) -> np.ndarray:
+                            m: int = 48, max_substeps: int = 100000, stats: dict = None,
+                            stop_after: int = 0) -> np.ndarray:
+    """``stop_after`` > 0 ends the run after that many substeps (a partial
+    result for timing samples); ``stats`` receives substeps, matvecs and the
+    time t reached."""
     vectors = [np.asarray(v, dtype=np.float64) for v in vectors]
     p = len(vectors) - 1
     N = vectors[0].size
@@ -101,6 +105,8 @@ def phi_combination_arnoldi(apply_A: Callable[[np.ndarray], np.ndarray], T: floa
         if T - t <= 8.0 * np.finfo(float).eps * T:
             t = T
         dt = 1.5 * dt
+        if stop_after and substeps >= stop_after:
+            break
     if stats is not None:
-        stats.update(substeps=substeps, matvecs=matvecs)
+        stats.update(substeps=substeps, matvecs=matvecs, t=t)
     return w

@@ -61,6 +61,9 @@ class Stats(C.Structure):
         ("matvecs", C.c_int64),
         ("last_omega", C.c_double), ("t_reached", C.c_double), ("alg_bytes", C.c_double),
         ("beta_last", C.c_double),
+        ("time_work_s", C.c_double), ("time_wait_s", C.c_double), ("time_epilogue_s", C.c_double),
+        ("time_expm_s", C.c_double), ("arrive_max_s", C.c_double), ("arrive_mean_s", C.c_double),
+        ("barriers", C.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -119,6 +122,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime under the same soname; importing it first
+    # makes this library bind to that one runtime instead of loading a second
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
     lib = C.CDLL(path)

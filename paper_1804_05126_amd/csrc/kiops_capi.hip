@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -32,7 +33,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t ctrl, bar, H, G, Y, sinv, unorm, partials, expm, trace, slots, bcopy, coef, total;
+  size_t params, ctrl, bar, arrive, arrive_t, H, G, Y, sinv, unorm, partials, expm, trace, slots, bcopy, coef, total;
   int nwg, ndot_stride;
 };
 
@@ -45,33 +46,48 @@ int coef_streams(const kiops_operator* op) {
   return c;
 }
 
-// The kernel instantiation that serves an operator.
-const void* kernel_for(const kiops_operator* op) {
+// Compile-time bound on p used by the stencil passes.
+int p_bucket(int p) { return p == 0 ? 0 : (p <= 2 ? 2 : (p <= 4 ? 4 : 8)); }
+
+template <typename T>
+const void* stencil2d_kernel(int pb) {
+  switch (pb) {
+    case 0: return (const void*)kiops_solve_kernel<Stencil2D<T, 0>, T>;
+    case 2: return (const void*)kiops_solve_kernel<Stencil2D<T, 2>, T>;
+    case 4: return (const void*)kiops_solve_kernel<Stencil2D<T, 4>, T>;
+    default: return (const void*)kiops_solve_kernel<Stencil2D<T, 8>, T>;
+  }
+}
+
+// The kernel instantiation that serves an operator and p.
+const void* kernel_for(const kiops_operator* op, int p) {
   if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
-    if (op->d.precision == KIOPS_MIXED) return (const void*)kiops_solve_kernel<Stencil2D<float>, float>;
-    return (const void*)kiops_solve_kernel<Stencil2D<double>, double>;
+    if (op->d.precision == KIOPS_MIXED) return stencil2d_kernel<float>(p_bucket(p));
+    return stencil2d_kernel<double>(p_bucket(p));
   }
   return nullptr;
 }
 
 int64_t work_tiles(const kiops_operator* op) {
   if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
-    const int64_t tx = (op->d.nx + Stencil2D<double>::TX - 1) / Stencil2D<double>::TX;
-    const int64_t ty = (op->d.ny + Stencil2D<double>::TY - 1) / Stencil2D<double>::TY;
+    const int64_t tx = (op->d.nx + Stencil2D<double, 2>::TX - 1) / Stencil2D<double, 2>::TX;
+    const int64_t ty = (op->d.ny + Stencil2D<double, 2>::TY - 1) / Stencil2D<double, 2>::TY;
     return tx * ty;
   }
   return 1;
 }
 
 // Persistent grid: all workgroups co-resident, no more than the tiles of work.
-kiops_status grid_size(const kiops_operator* op, int* nwg) {
-  const void* fn = kernel_for(op);
+kiops_status grid_size(const kiops_operator* op, int p, int* nwg) {
+  const void* fn = kernel_for(op, p);
   if (!fn) return KIOPS_ERR_UNSUPPORTED;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess || per_cu < 1)
     return KIOPS_ERR_DEVICE;
   int64_t g = (int64_t)per_cu * op->cus;
-  g = std::min<int64_t>(g, std::max<int64_t>(1, work_tiles(op)));
+  const char* ov = std::getenv("KIOPS_GRID");   // experiment override, capped by co-residency
+  if (ov && std::atoi(ov) > 0) g = std::min<int64_t>(g, std::atoi(ov));
+  else g = std::min<int64_t>(g, std::max<int64_t>(1, work_tiles(op)));
   *nwg = (int)g;
   return KIOPS_OK;
 }
@@ -89,8 +105,11 @@ Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
   L.nwg = nwg;
   L.ndot_stride = std::max(kPM, kDotSlots);
   (void)q;
+  L.params = take(4096);   // KParams followed by the operator struct
   L.ctrl = take(sizeof(Ctrl));
   L.bar = take(sizeof(Barrier));
+  L.arrive = take(sizeof(unsigned) * (size_t)nwg);
+  L.arrive_t = take(sizeof(uint64_t) * (size_t)nwg);
   L.H = take(sizeof(double) * kLdh * kLdh);
   L.G = take(sizeof(double) * kLdh * kLdh);
   L.Y = take(sizeof(double) * kLdh * kPM);
@@ -109,16 +128,16 @@ Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
 
 bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
-template <typename T>
-Stencil2D<T> make_stencil2d(const kiops_operator* op, int p, const double* const* V, char* ws,
-                            const Layout& L) {
+template <typename T, int PB>
+Stencil2D<T, PB> make_stencil2d(const kiops_operator* op, int p, const double* const* V, char* ws,
+                                const Layout& L) {
   const auto& d = op->d;
-  Stencil2D<T> s{};
+  Stencil2D<T, PB> s{};
   s.N = op->N;
   s.nx = (int)d.nx;
   s.ny = (int)d.ny;
-  s.tiles_x = (int)((d.nx + Stencil2D<T>::TX - 1) / Stencil2D<T>::TX);
-  const int tiles_y = (int)((d.ny + Stencil2D<T>::TY - 1) / Stencil2D<T>::TY);
+  s.tiles_x = (int)((d.nx + Stencil2D<T, PB>::TX - 1) / Stencil2D<T, PB>::TX);
+  const int tiles_y = (int)((d.ny + Stencil2D<T, PB>::TY - 1) / Stencil2D<T, PB>::TY);
   s.ntiles = s.tiles_x * tiles_y;
   const double cD = d.diff / (d.h * d.h);
   const double cx = d.adv[0] / (2.0 * d.h);
@@ -172,6 +191,10 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   P.bcopy = ws + L.bcopy;
   P.ctrl = reinterpret_cast<Ctrl*>(ws + L.ctrl);
   P.bar = reinterpret_cast<Barrier*>(ws + L.bar);
+  P.arrive = reinterpret_cast<unsigned*>(ws + L.arrive);
+  P.arrive_t = reinterpret_cast<uint64_t*>(ws + L.arrive_t);
+  const char* prof = std::getenv("KIOPS_PROFILE");
+  P.profile = (prof && std::atoi(prof) > 0) ? 1 : 0;
   P.H = reinterpret_cast<double*>(ws + L.H);
   P.G = reinterpret_cast<double*>(ws + L.G);
   P.Y = reinterpret_cast<double*>(ws + L.Y);
@@ -183,27 +206,48 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   return P;
 }
 
+template <class OpT>
+void stage_op(unsigned char* host_block, const OpT& o) {
+  static_assert(sizeof(OpT) <= 2048, "operator block");
+  std::memcpy(host_block + 2048, &o, sizeof(OpT));
+}
+
 // Launch one persistent solve and wait for its control block.
 kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, const double* const* V,
                        Ctrl* host_ctrl, unsigned* host_abort) {
   char* ws = reinterpret_cast<char*>(op->ws);
-  hipLaunchKernelGGL(kiops_reset_kernel, dim3(1), dim3(64), 0, op->stream, P.bar, P.ctrl);
+  hipLaunchKernelGGL(kiops_reset_kernel, dim3(1), dim3(256), 0, op->stream, P.bar, P.ctrl, P.arrive, L.nwg);
   if (!hip_ok(hipGetLastError())) return KIOPS_ERR_DEVICE;
   hipError_t e = hipSuccess;
+  // parameter block: KParams at +0, operator struct at +2048 (host staging buffer)
+  static_assert(sizeof(KParams) <= 2048, "params block");
+  alignas(256) unsigned char host_block[4096];
+  std::memset(host_block, 0, sizeof(host_block));
+  std::memcpy(host_block, &P, sizeof(KParams));
+  KParams* dP = reinterpret_cast<KParams*>(ws + L.params);
+  void* dOp = ws + L.params + 2048;
+  const void* fn = kernel_for(op, p);
+  if (!fn) return KIOPS_ERR_UNSUPPORTED;
   if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
-    if (op->d.precision == KIOPS_MIXED) {
-      auto s = make_stencil2d<float>(op, p, V, ws, L);
-      void* args[] = {&P, &s};
-      e = hipLaunchCooperativeKernel((const void*)kiops_solve_kernel<Stencil2D<float>, float>,
-                                     dim3(L.nwg), dim3(kThreads), args, 0, op->stream);
-    } else {
-      auto s = make_stencil2d<double>(op, p, V, ws, L);
-      void* args[] = {&P, &s};
-      e = hipLaunchCooperativeKernel((const void*)kiops_solve_kernel<Stencil2D<double>, double>,
-                                     dim3(L.nwg), dim3(kThreads), args, 0, op->stream);
+    const bool mixed = op->d.precision == KIOPS_MIXED;
+    switch (p_bucket(p)) {
+      case 0: mixed ? stage_op(host_block, make_stencil2d<float, 0>(op, p, V, ws, L))
+                    : stage_op(host_block, make_stencil2d<double, 0>(op, p, V, ws, L)); break;
+      case 2: mixed ? stage_op(host_block, make_stencil2d<float, 2>(op, p, V, ws, L))
+                    : stage_op(host_block, make_stencil2d<double, 2>(op, p, V, ws, L)); break;
+      case 4: mixed ? stage_op(host_block, make_stencil2d<float, 4>(op, p, V, ws, L))
+                    : stage_op(host_block, make_stencil2d<double, 4>(op, p, V, ws, L)); break;
+      default: mixed ? stage_op(host_block, make_stencil2d<float, 8>(op, p, V, ws, L))
+                     : stage_op(host_block, make_stencil2d<double, 8>(op, p, V, ws, L)); break;
     }
   } else {
     return KIOPS_ERR_UNSUPPORTED;
+  }
+  if (!hip_ok(hipMemcpyAsync(dP, host_block, sizeof(host_block), hipMemcpyHostToDevice, op->stream)))
+    return KIOPS_ERR_DEVICE;
+  {
+    void* args[] = {&dP, &dOp};
+    e = hipLaunchCooperativeKernel(fn, dim3(L.nwg), dim3(kThreads), args, 0, op->stream);
   }
   if (!hip_ok(e)) return KIOPS_ERR_DEVICE;
   Barrier hb{};
@@ -216,8 +260,15 @@ kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, c
   return KIOPS_OK;
 }
 
-void fill_stats(const Ctrl& c, int nwg, kiops_stats* st) {
+void fill_stats(const Ctrl& c, int nwg, double clock_hz, kiops_stats* st) {
   if (!st) return;
+  st->time_work_s = (double)c.t_work / clock_hz;
+  st->time_wait_s = (double)c.t_wait / clock_hz;
+  st->time_epilogue_s = (double)c.t_epi / clock_hz;
+  st->time_expm_s = (double)c.t_expm / clock_hz;
+  st->arrive_max_s = (double)c.t_arrive_max / clock_hz;
+  st->arrive_mean_s = (double)c.t_arrive_mean / clock_hz;
+  st->barriers = (int64_t)c.n_barriers;
   st->m_last = c.m;
   st->substeps = c.substeps;
   st->rejections = c.rejections;
@@ -354,7 +405,7 @@ kiops_status kiops_device_info(const kiops_operator* op, int* compute_units, int
   if (compute_units) *compute_units = op->cus;
   if (grid_blocks) {
     int g = 0;
-    kiops_status s = grid_size(op, &g);
+    kiops_status s = grid_size(op, 2, &g);
     if (s != KIOPS_OK) return s;
     *grid_blocks = g;
   }
@@ -368,7 +419,7 @@ kiops_status kiops_workspace_bytes(const kiops_operator* op, int p, int q, const
   resolve_options(opts, &m_min, &m_max, &max_sub);
   if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max) return KIOPS_ERR_INVALID_ARG;
   int nwg = 0;
-  kiops_status s = grid_size(op, &nwg);
+  kiops_status s = grid_size(op, p, &nwg);
   if (s != KIOPS_OK) return s;
   *bytes = make_layout(op, p, q, m_max, nwg).total;
   return KIOPS_OK;
@@ -405,7 +456,7 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
     return KIOPS_OK;
   }
   int nwg = 0;
-  s = grid_size(op, &nwg);
+  s = grid_size(op, p, &nwg);
   if (s != KIOPS_OK) return s;
   const Layout L = make_layout(op, p, q, m_max, nwg);
   if (!op->ws || op->ws_bytes < L.total) return KIOPS_ERR_OUT_OF_MEMORY;
@@ -415,7 +466,7 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
   unsigned abort_flag = 0;
   s = run_solve(op, L, P, p, V, &hc, &abort_flag);
   if (s != KIOPS_OK) return s;
-  fill_stats(hc, nwg, stats);
+  fill_stats(hc, nwg, (double)op->clock_hz, stats);
   if (abort_flag) return KIOPS_ERR_DEVICE;
   return (kiops_status)hc.status;
 }
@@ -429,7 +480,7 @@ kiops_status kiops_iop_basis(kiops_operator* op, int p, const double* const* V, 
     if (!V[k]) return KIOPS_ERR_INVALID_ARG;
   if (op->d.kind != KIOPS_OP_STENCIL2D_5PT || op->d.kappa) return KIOPS_ERR_UNSUPPORTED;
   int nwg = 0;
-  kiops_status s = grid_size(op, &nwg);
+  kiops_status s = grid_size(op, p, &nwg);
   if (s != KIOPS_OK) return s;
   const Layout L = make_layout(op, p, q, m, nwg);
   // w holds b_0 during the run: place it in the last slot row of the workspace tail

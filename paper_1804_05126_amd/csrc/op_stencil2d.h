@@ -9,21 +9,57 @@
 // is staged in LDS over the tile plus a halo of two; U_{kp-1} and then R_kp
 // are formed on the tile plus a halo of one (a second LDS buffer); the
 // stencil of R_kp gives U_kp on the tile.  Each thread owns one column of four
-// consecutive rows of the tile, so loads and stores of a wave cover 64
-// consecutive doubles of a row.
+// consecutive rows of the tile (plus at most one position of the halo ring),
+// so a wave's loads and stores cover 64 consecutive elements of a row.
+//
+// Every global load of a tile (the halo-2 region of R_{kp-1} and, at the
+// thread's five positions, r, the p columns of B and the older window vector)
+// is issued before the first use, so a tile costs one memory round trip.
+// PB bounds p at compile time so that these loads land in registers.  All
+// arrays are addressed as uniform base + 32-bit byte offset (one offset per
+// position serves every array), so an array is limited to 4 GiB.
 #pragma once
 
 #include "pass_common.h"
 
 namespace kiops {
 
-template <typename T>
+// Buffer resources (gfx9 raw buffers): a load whose byte offset lies outside
+// [0, num_records) returns zero without touching memory, and such a store is
+// dropped.  Absent arrays get num_records = 0, absent positions an offset of
+// kNoOffset, so every load of a tile can be issued unconditionally.
+constexpr uint32_t kNoOffset = 0xFFFFFFF0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint64_t bytes) {
+  const int n = (p && bytes < 0xFFFFFFFFull) ? (int)(uint32_t)bytes : 0;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, n, 0x00020000);
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+typedef unsigned int kiops_u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(kiops_u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+
+template <typename T, int PB>
 struct Stencil2D {
   static constexpr int TX = 64, TY = 16;
   static constexpr int RX = TX + 4, RY = TY + 4;   // halo-2 region (R_{kp-1})
   static constexpr int SX = TX + 2, SY = TY + 2;   // halo-1 region (R_kp)
-  static constexpr int kRing = SX * SY - TX * TY;  // halo-1 positions outside the tile
+  static constexpr int kRingPos = SX * SY - TX * TY;  // halo-1 positions outside the tile
+  static constexpr int kRegion = RX * RY;
+  static constexpr int kRegionLoads = (kRegion + kThreads - 1) / kThreads;
+  static constexpr int kPos = 5;                   // 4 tile positions + 1 ring position
   static constexpr int kLdsT = RX * RY + SX * SY;  // elements of T
+  // occupancy target: the register footprint of a tile's loads grows with PB
+  static constexpr int kWavesPerEU = (PB >= 4 && sizeof(T) == 8) ? 3 : 4;
 
   int64_t N;
   int nx, ny, tiles_x, ntiles;
@@ -39,8 +75,8 @@ struct Stencil2D {
       for (int64_t n = gt; n < P.N; n += gs) r_dst[n] = (T)r_src[n];
   }
 
-  __device__ void ring_pos(int e, int& rx, int& ry) const {
-    // e in [0, kRing): top row, bottom row, left column, right column of the halo-1 ring
+  __device__ static void ring_pos(int e, int& rx, int& ry) {
+    // e in [0, kRingPos): top row, bottom row, left column, right column of the halo-1 ring
     if (e < SX) { rx = e - 1; ry = -1; return; }
     e -= SX;
     if (e < SX) { rx = e - 1; ry = TY; return; }
@@ -50,45 +86,6 @@ struct Stencil2D {
     rx = TX; ry = e;
   }
 
-  // Form R_kp at halo-1 position (rx, ry) of the tile at (x0, y0); store into sX.
-  // Returns r and the B term of U_kp at that position (used on the tile).
-  __device__ __forceinline__ void form(const PassCtx<T>& c, const BasisPtrs<T>& bp, const double* w,
-                                       const T* sR, T* sX, int x0, int y0, int rx, int ry,
-                                       T& rv, T& bcur) const {
-    const int gx = wrap_index(x0 + rx, nx);
-    const int gy = wrap_index(y0 + ry, ny);
-    const int64_t g = (int64_t)gy * nx + gx;
-    rv = r ? r[g] : T(0);
-    T bprev = T(0);
-    bcur = T(0);
-#pragma unroll
-    for (int k = 0; k < kPM; ++k) {
-      if (k < c.p) {
-        const T bv = B[k][g];
-        bprev = fma(bv, c.ybp[k], bprev);
-        bcur = fma(bv, c.ybc[k], bcur);
-      }
-    }
-    T X;
-    if (c.first) {
-      X = (T)w[g];
-    } else {
-      const int o = (ry + 2) * RX + (rx + 2);
-      const T ctr = sR[o];
-      T U = wE * sR[o + 1];
-      U = fma(wW, sR[o - 1], U);
-      U = fma(wN, sR[o + RX], U);
-      U = fma(wS, sR[o - RX], U);
-      U = fma(wC + rv, ctr, U);
-      U += bprev;
-      X = c.a * U;
-      X = fma(c.bw[c.src], ctr, X);
-      for (int i = c.flo; i < c.src; ++i) X = fma(c.bw[i], bp.get(i)[g], X);
-    }
-    sX[(ry + 1) * SX + (rx + 1)] = X;
-  }
-
-  // One pass over the tiles owned by this workgroup (windowed inner products).
   __device__ void pass(const PassCtx<T>& c, const BasisPtrs<T>& bp, const double* w, T* Rout,
                        DotAcc& acc, T* lds) const {
     T* sR = lds;
@@ -96,56 +93,122 @@ struct Stencil2D {
     const int t = threadIdx.x;
     const int cx = t & (TX - 1);
     const int rg = (t >> 6) * 4;
-    const T* Rsrc = c.first ? nullptr : bp.get(c.src);
+    const bool first = c.first != 0;
+    const uint64_t nb = (uint64_t)N * sizeof(T);
+    const bool has_old = !first && c.flo < c.src;          // R_{kp-2} in the window
+    const bool more_old = !first && c.flo < c.src - 1;     // windows wider than 2
+    const __amdgpu_buffer_rsrc_t rsR = make_rsrc(first ? nullptr : bp.get(c.src), nb);
+    const __amdgpu_buffer_rsrc_t rsO = make_rsrc(has_old ? bp.get(c.src - 1) : nullptr, nb);
+    const __amdgpu_buffer_rsrc_t rsW = make_rsrc(first ? w : nullptr, (uint64_t)N * 8);
+    const __amdgpu_buffer_rsrc_t rsr = make_rsrc(r, nb);
+    const __amdgpu_buffer_rsrc_t rsOut = make_rsrc(c.write_out ? Rout : nullptr, nb);
+    __amdgpu_buffer_rsrc_t rsB[PB > 0 ? PB : 1];
+#pragma unroll
+    for (int k = 0; k < PB; ++k) rsB[k] = make_rsrc(k < c.p ? B[k] : nullptr, nb);
+    int prx[kPos], pry[kPos];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { prx[i] = cx; pry[i] = rg + i; }
+    const bool ring = t < kRingPos;
+    ring_pos(ring ? t : 0, prx[4], pry[4]);
+
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
       const int x0 = (tile % tiles_x) * TX;
       const int y0 = (tile / tiles_x) * TY;
-      if (!c.first) {
-        for (int e = t; e < RX * RY; e += kThreads) {
-          const int ry2 = e / RX, rx2 = e - ry2 * RX;
-          const int gx = wrap_index(x0 - 2 + rx2, nx);
-          const int gy = wrap_index(y0 - 2 + ry2, ny);
-          sR[e] = Rsrc[(int64_t)gy * nx + gx];
-        }
-        __syncthreads();
-      }
-      T rv[4], bc[4];
+      // ---- issue every load of the tile
+      T reg[kRegionLoads];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) form(c, bp, w, sR, sX, x0, y0, cx, rg + i, rv[i], bc[i]);
-      if (t < kRing) {
-        int rx, ry;
-        ring_pos(t, rx, ry);
-        T dr, db;
-        form(c, bp, w, sR, sX, x0, y0, rx, ry, dr, db);
+      for (int i = 0; i < kRegionLoads; ++i) {
+        const int e = t + i * kThreads;
+        const int ry2 = e / RX, rx2 = e - ry2 * RX;
+        const int gx = wrap_index(x0 - 2 + rx2, nx);
+        const int gy = wrap_index(y0 - 2 + ry2, ny);
+        const uint32_t off = (e < kRegion) ? (uint32_t)(gy * nx + gx) * (uint32_t)sizeof(T) : kNoOffset;
+        reg[i] = buf_ld(rsR, off, T(0));
+      }
+      uint32_t goff[kPos];
+      T rv[kPos], ov[kPos], bv[kPos][PB > 0 ? PB : 1];
+#pragma unroll
+      for (int q = 0; q < kPos; ++q) {
+        const int gx = wrap_index(x0 + prx[q], nx);
+        const int gy = wrap_index(y0 + pry[q], ny);
+        const uint32_t idx = (uint32_t)(gy * nx + gx);
+        goff[q] = (q < 4 || ring) ? idx * (uint32_t)sizeof(T) : kNoOffset;
+        rv[q] = buf_ld(rsr, goff[q], T(0));
+        if (first) ov[q] = (T)buf_ld(rsW, (q < 4 || ring) ? idx * 8u : kNoOffset, 0.0);
+        else ov[q] = buf_ld(rsO, goff[q], T(0));
+#pragma unroll
+        for (int k = 0; k < PB; ++k) bv[q][k] = buf_ld(rsB[k], goff[q], T(0));
+      }
+      // ---- R_{kp-1} region into LDS
+      if (!first) {
+#pragma unroll
+        for (int i = 0; i < kRegionLoads; ++i) {
+          const int e = t + i * kThreads;
+          if (e < kRegion) sR[e] = reg[i];
+        }
       }
       __syncthreads();
+      // ---- form R_kp on the halo-1 region
+      T bcur[4];
+#pragma unroll
+      for (int q = 0; q < kPos; ++q) {
+        if (q < 4 || ring) {
+          T bprev = T(0), bc = T(0);
+#pragma unroll
+          for (int k = 0; k < PB; ++k) {
+            bprev = fma(bv[q][k], c.ybp[k], bprev);
+            bc = fma(bv[q][k], c.ybc[k], bc);
+          }
+          if (q < 4) bcur[q] = bc;
+          T X;
+          if (first) {
+            X = ov[q];
+          } else {
+            const int o = (pry[q] + 2) * RX + (prx[q] + 2);
+            const T ctr = sR[o];
+            T U = wE * sR[o + 1];
+            U = fma(wW, sR[o - 1], U);
+            U = fma(wN, sR[o + RX], U);
+            U = fma(wS, sR[o - RX], U);
+            U = fma(wC + rv[q], ctr, U);
+            U += bprev;
+            X = c.a * U;
+            X = fma(c.bw[c.src], ctr, X);
+            if (has_old) X = fma(c.bw[c.src - 1], ov[q], X);
+            if (more_old)
+              for (int i = c.flo; i < c.src - 1; ++i)
+                X = fma(c.bw[i], buf_ld(make_rsrc(bp.get(i), nb), goff[q], T(0)), X);
+          }
+          sX[(pry[q] + 1) * SX + (prx[q] + 1)] = X;
+        }
+      }
+      __syncthreads();
+      // ---- U_kp on the tile, output and inner products
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int ry = rg + i;
-        if (x0 + cx < nx && y0 + ry < ny) {
-          const int o = (ry + 1) * SX + (cx + 1);
-          const T X = sX[o];
-          T U = wE * sX[o + 1];
-          U = fma(wW, sX[o - 1], U);
-          U = fma(wN, sX[o + SX], U);
-          U = fma(wS, sX[o - SX], U);
-          U = fma(wC + rv[i], X, U);
-          U += bc[i];
-          const int64_t g = (int64_t)(y0 + ry) * nx + (x0 + cx);
-          if (c.write_out) Rout[g] = X;
-          const double Xd = (double)X, Ud = (double)U;
-          acc.RR = fma(Xd, Xd, acc.RR);
-          acc.UU = fma(Ud, Ud, acc.UU);
-          acc.Ck = fma(Xd, Ud, acc.Ck);
+        const bool valid = (x0 + cx < nx) && (y0 + ry < ny);
+        const int o = (ry + 1) * SX + (cx + 1);
+        const T X = sX[o];
+        T U = wE * sX[o + 1];
+        U = fma(wW, sX[o - 1], U);
+        U = fma(wN, sX[o + SX], U);
+        U = fma(wS, sX[o - SX], U);
+        U = fma(wC + rv[i], X, U);
+        U += bcur[i];
+        buf_st(rsOut, valid ? goff[i] : kNoOffset, X);
+        const double Xd = valid ? (double)X : 0.0, Ud = valid ? (double)U : 0.0;
+        acc.RR = fma(Xd, Xd, acc.RR);
+        acc.UU = fma(Ud, Ud, acc.UU);
+        acc.Ck = fma(Xd, Ud, acc.Ck);
 #pragma unroll
-          for (int d = 0; d < kWinMax - 1; ++d) {
-            if (d < c.ngd) {
-              const int idx = c.dlo + d;
-              const double Rv = (idx == c.src) ? (double)sR[(ry + 2) * RX + (cx + 2)]
-                                               : (double)bp.get(idx)[g];
-              acc.G[d] = fma(Rv, Xd, acc.G[d]);
-              acc.C[d] = fma(Rv, Ud, acc.C[d]);
-            }
+        for (int d = 0; d < kWinMax - 1; ++d) {
+          if (d < c.ngd) {
+            const int idx = c.dlo + d;
+            const double Rv = (idx == c.src) ? (double)sR[(ry + 2) * RX + (cx + 2)]
+                                             : (double)buf_ld(make_rsrc(bp.get(idx), nb), goff[i], T(0));
+            acc.G[d] = fma(Rv, Xd, acc.G[d]);
+            acc.C[d] = fma(Rv, Ud, acc.C[d]);
           }
         }
       }

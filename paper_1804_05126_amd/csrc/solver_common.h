@@ -53,6 +53,11 @@ struct Ctrl {
   int64_t matvecs;
   double last_omega, alg_bytes;
   double s_last;
+  // phase timers of workgroup 0, in ticks of the constant-rate clock:
+  // its own pass work, waiting for the other workgroups, epilogues
+  uint64_t t_work, t_wait, t_epi, t_last;
+  // optional profile: small exponentials, latest / mean arrival after a release
+  uint64_t t_expm, t_arrive_max, t_arrive_mean, n_barriers;
 };
 
 struct Barrier {
@@ -67,6 +72,7 @@ struct KParams {
   int64_t N;
   int p, q, m_min, m_max, m_init, max_substeps;
   int mode, mixed, nwg, ndot_stride;
+  int profile;                 // record per-workgroup arrival times (diagnostics)
   double T_end, tol;
   double elem_bytes;           // bytes per basis element (8 or 4)
   double coef_streams;         // per-cell coefficient arrays the operator reads
@@ -77,6 +83,8 @@ struct KParams {
   void* bcopy;                 // mixed: float copies of B columns
   Ctrl* ctrl;
   Barrier* bar;
+  unsigned* arrive;            // per-workgroup arrival epochs (grid barrier)
+  uint64_t* arrive_t;          // per-workgroup arrival clocks (profile only)
   double* H;                   // kLdh x kLdh
   double* G;                   // Gram matrix of the normalised basis, kLdh x kLdh
   double* Y;                   // trailing (y) parts of R_i, kLdh x kPM

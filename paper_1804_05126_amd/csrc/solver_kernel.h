@@ -6,8 +6,12 @@
 //   attempt: F = exp(tau H~) (Eqs. (37)-(38)), eps (Eq. (36)), Algorithm 4
 //   accept:  w <- beta V(1:N, 1:j) F(1:j, 1) (Algorithm 3, Eq. (33))
 //
-// Every phase ends in a grid barrier whose last arriving workgroup runs the
-// serial epilogue; all workgroups then read the next phase from Ctrl.
+// Every phase ends in a grid barrier.  Workgroup 0 collects the arrivals,
+// runs the serial epilogue and releases the grid.  The solver's small state
+// (control block, normalisations, the band of H, the window of the Gram
+// matrix and of the trailing parts) lives in workgroup 0's LDS for the whole
+// solve; after each epilogue the control block is published to device memory,
+// where the other workgroups read the next phase and its coefficients.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,50 +23,134 @@
 
 namespace kiops {
 
-constexpr int kLdsDoubles = 3600;   // union: pass tiles / expm staging / reductions
+constexpr int kLdsDoubles = 2600;           // union: pass tiles / expm staging
+constexpr int kRingRows = kWinMax + 2;      // ring of trailing parts and Gram rows
 
 #define KIOPS_AGENT __HIP_MEMORY_SCOPE_AGENT
 
-// Wait until the barrier generation moves past g.  Bounded: a wait longer than
-// spin_limit ticks of the constant-rate clock raises the abort flag so that
-// every workgroup leaves the kernel.
-__device__ inline bool barrier_wait(Barrier* b, unsigned g, uint64_t spin_limit) {
-  const uint64_t t0 = (uint64_t)wall_clock64();
-  while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT) == g) {
-    if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, KIOPS_AGENT)) return false;
-    __builtin_amdgcn_s_sleep(2);
-    if ((uint64_t)wall_clock64() - t0 > spin_limit) {
-      __hip_atomic_store(&b->abort, 1u, __ATOMIC_RELAXED, KIOPS_AGENT);
-      return false;
-    }
+// Small state of workgroup 0 (LDS).
+struct SmallState {
+  Ctrl C;
+  double sinv[kLdh];                 // v_i = R_i * sinv[i]
+  double Hb[kLdh][kWinMax + 1];      // Hb[k][d] = H(k - kWinMax + 1 + d, k)
+  double Yw[kRingRows][kPM];         // y-part of R_i at row i % kRingRows
+  double Gw[kRingRows][kWinMax];     // Gw[k % kRingRows][d] = G(k, k - kWinMax + 1 + d)
+  double unorm_prev;                 // ||A~ v_{kp-1}||
+  double red[16];                    // reduced inner products
+  int action, jj, again, expired;
+};
+
+__device__ inline double h_get(const SmallState& S, int i, int k) {
+  const int d = i - (k - kWinMax + 1);
+  return (d >= 0 && d <= kWinMax) ? S.Hb[k][d] : 0.0;
+}
+__device__ inline void h_set(SmallState& S, const KParams& P, int i, int k, double v) {
+  S.Hb[k][i - (k - kWinMax + 1)] = v;
+  P.H[i * kLdh + k] = v;                      // device-memory copy (diagnostics export)
+}
+__device__ inline double g_get(const SmallState& S, int i, int l) {   // |i - l| < kWinMax
+  if (i < l) { const int t = i; i = l; l = t; }
+  return S.Gw[i % kRingRows][l - (i - kWinMax + 1)];
+}
+__device__ inline double* y_row(SmallState& S, int i) { return S.Yw[i % kRingRows]; }
+
+__device__ inline bool spin_expired(Barrier* b, uint64_t t0, uint64_t spin_limit) {
+  if (__hip_atomic_load(&b->abort, __ATOMIC_RELAXED, KIOPS_AGENT)) return true;
+  if ((uint64_t)wall_clock64() - t0 > spin_limit) {
+    __hip_atomic_store(&b->abort, 1u, __ATOMIC_RELAXED, KIOPS_AGENT);
+    return true;
   }
-  return true;
+  return false;
 }
 
-// Grid barrier; the last workgroup to arrive runs `epi` (whole workgroup)
-// before the others are released.
+// Grid barrier without contended atomics.  Workgroup w publishes its arrival
+// by storing the barrier epoch into arrive[w]; workgroup 0 waits until every
+// slot holds the epoch, runs `epi`, and releases the grid by storing the epoch
+// into `gen`.  Every wait is bounded by spin_limit ticks of the constant-rate
+// clock; on expiry the abort flag is raised and all workgroups leave.
 template <class F>
-__device__ inline void grid_barrier(Barrier* b, unsigned nwg, uint64_t spin_limit, F&& epi) {
-  __shared__ int s_last;
+__device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& epoch, F&& epi) {
+  Barrier* b = P.bar;
+  ++epoch;
+  // The workgroup's stores are ordered before thread 0's agent-scope release
+  // (one L2 write-back per workgroup rather than one per wave).
+  __syncthreads();
+  if (blockIdx.x != 0) {
+    if (threadIdx.x == 0) {
+      if (P.profile) P.arrive_t[blockIdx.x] = (uint64_t)wall_clock64();
+      __threadfence();
+      __hip_atomic_store(&P.arrive[blockIdx.x], epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
+      const uint64_t t0 = (uint64_t)wall_clock64();
+      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT) != epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (spin_expired(b, t0, P.spin_limit)) break;
+      }
+      __threadfence();
+    }
+    __syncthreads();
+    return;
+  }
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  for (;;) {
+    int ok = 1;
+    for (unsigned w = 1 + threadIdx.x; w < (unsigned)P.nwg; w += kThreads)
+      ok &= (__hip_atomic_load(&P.arrive[w], __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) ? 1 : 0;
+    if (__syncthreads_and(ok)) break;
+    if (threadIdx.x == 0) {                      // the give-up decision is thread 0's
+      __builtin_amdgcn_s_sleep(1);
+      S.expired = spin_expired(b, t0, P.spin_limit) ? 1 : 0;
+    }
+    __syncthreads();
+    if (S.expired) break;
+  }
+  __threadfence();
+  __syncthreads();
+  const uint64_t t1 = (uint64_t)wall_clock64();
+  if (P.profile) {
+    // arrival spread: latest and mean arrival after the previous release
+    uint64_t mx = 0, sum = 0;
+    for (int w = 1 + threadIdx.x; w < P.nwg; w += kThreads) {
+      const uint64_t a = P.arrive_t[w] - S.C.t_last;
+      mx = a > mx ? a : mx;
+      sum += a;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t om = __shfl_down(mx, off, 64);
+      const uint64_t os = __shfl_down(sum, off, 64);
+      mx = om > mx ? om : mx;
+      sum += os;
+    }
+    __shared__ uint64_t s_mx[kThreads / 64], s_sum[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) { s_mx[threadIdx.x >> 6] = mx; s_sum[threadIdx.x >> 6] = sum; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 1; q < kThreads / 64; ++q) { mx = s_mx[q] > mx ? s_mx[q] : mx; sum += s_sum[q]; }
+      mx = s_mx[0] > mx ? s_mx[0] : mx;
+      S.C.t_arrive_max += mx;
+      S.C.t_arrive_mean += P.nwg > 1 ? sum / (uint64_t)(P.nwg - 1) : 0;
+      S.C.n_barriers += 1;
+    }
+    __syncthreads();
+  }
+  epi();
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned g = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT);
-    const unsigned prev = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, KIOPS_AGENT);
-    int last = (prev == nwg - 1) ? 1 : 0;
-    if (!last) barrier_wait(b, g, spin_limit);
+    const uint64_t t2 = (uint64_t)wall_clock64();
+    Ctrl& C = S.C;
+    C.t_work += t0 - C.t_last;
+    C.t_wait += t1 - t0;
+    C.t_epi += t2 - t1;
+    C.t_last = t2;
+    P.ctrl->t_work = C.t_work;
+    P.ctrl->t_wait = C.t_wait;
+    P.ctrl->t_epi = C.t_epi;
+    P.ctrl->t_expm = C.t_expm;
+    P.ctrl->t_arrive_max = C.t_arrive_max;
+    P.ctrl->t_arrive_mean = C.t_arrive_mean;
+    P.ctrl->n_barriers = C.n_barriers;
     __threadfence();
-    s_last = last;
-  }
-  __syncthreads();
-  if (s_last) {
-    epi();
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, KIOPS_AGENT);
-      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, KIOPS_AGENT);
-    }
+    __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
   }
   __syncthreads();
 }
@@ -71,42 +159,70 @@ __device__ inline bool aborted(const KParams& P) {
   return __hip_atomic_load(&P.bar->abort, __ATOMIC_RELAXED, KIOPS_AGENT) != 0;
 }
 
-// Deterministic reduction of the per-workgroup partials: out[d] = sum_wg partials[wg][d]
-// summed in workgroup order, for d < ndots.  Result in LDS `out` (all threads).
-__device__ inline void reduce_partials(const KParams& P, int ndots, double* out) {
-  const int t = threadIdx.x;
-  if (ndots <= 16) {
-    const int d = t >> 4, lane = t & 15;
+// out[d] = sum over workgroups of partials[wg][d], d < kDotSlots, in a fixed
+// order (workgroup index, then lanes, then waves).  All loads are issued
+// before the first add.
+__device__ inline void reduce_partials(const KParams& P, double* out, double* lds) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double acc[kDotSlots];
+#pragma unroll
+  for (int d = 0; d < kDotSlots; ++d) acc[d] = 0.0;
+  int w = t;
+  for (; w + 3 * kThreads < P.nwg; w += 4 * kThreads) {
+    double v[4][kDotSlots];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int d = 0; d < kDotSlots; ++d) v[u][d] = P.partials[(int64_t)(w + u * kThreads) * P.ndot_stride + d];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int d = 0; d < kDotSlots; ++d) acc[d] += v[u][d];
+  }
+  for (; w < P.nwg; w += kThreads)
+#pragma unroll
+    for (int d = 0; d < kDotSlots; ++d) acc[d] += P.partials[(int64_t)w * P.ndot_stride + d];
+#pragma unroll
+  for (int d = 0; d < kDotSlots; ++d) {
+    double v = acc[d];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) lds[wv * 16 + d] = v;
+  }
+  __syncthreads();
+  if (t < kDotSlots) {
     double s = 0.0;
-    if (d < ndots)
-      for (int wgi = lane; wgi < P.nwg; wgi += 16) s += P.partials[(int64_t)wgi * P.ndot_stride + d];
-    for (int off = 8; off > 0; off >>= 1) s += __shfl_down(s, off, 16);
-    if (d < ndots && lane == 0) out[d] = s;
-  } else {
-    for (int d = t; d < ndots; d += kThreads) {
-      double s = 0.0;
-      for (int wgi = 0; wgi < P.nwg; ++wgi) s += P.partials[(int64_t)wgi * P.ndot_stride + d];
-      out[d] = s;
-    }
+    for (int q = 0; q < kThreads / 64; ++q) s += lds[q * 16 + t];
+    out[t] = s;
   }
   __syncthreads();
 }
 
-__device__ inline double& Hel(const KParams& P, int i, int l) { return P.H[i * kLdh + l]; }
-__device__ inline double& Gel(const KParams& P, int i, int l) { return P.G[i * kLdh + l]; }
-__device__ inline double* Yrow(const KParams& P, int i) { return P.Y + i * kPM; }
+// Copy the control block to device memory (all threads).
+__device__ inline void publish(const KParams& P, const SmallState& S) {
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(&S.C);
+  uint64_t* dst = reinterpret_cast<uint64_t*>(P.ctrl);
+  static_assert(sizeof(Ctrl) % 8 == 0, "control block layout");
+  for (int i = threadIdx.x; i < (int)(sizeof(Ctrl) / 8); i += kThreads) dst[i] = src[i];
+  __syncthreads();
+}
 
 // Start of a substep (thread 0): exact trailing entries mu [T^{p-1}/(p-1)!, ..., T, 1].
-__device__ inline void start_substep(const KParams& P) {
-  Ctrl& C = *P.ctrl;
-  double* y1 = Yrow(P, 1);
+__device__ inline void start_substep(const KParams& P, SmallState& S) {
+  Ctrl& C = S.C;
+  double* y1 = y_row(S, 1);
   const int p = C.p;
   double fact = 1.0;
+#pragma unroll
+  for (int c = 0; c < kPM; ++c) y1[c] = 0.0;
   for (int i = 0; i < p; ++i) {            // entry p-1-i holds T^i / i!
     if (i > 0) fact *= (double)i;
     y1[p - 1 - i] = C.mu * pow(C.T_now, (double)i) / fact;
   }
-  for (int c = 0; c < kPM; ++c) C.yb_cur[c] = (c < p) ? C.nu * y1[c] : 0.0;
+  for (int c = 0; c < kPM; ++c) {
+    C.yb_cur[c] = (c < p) ? C.nu * y1[c] : 0.0;
+    C.yb_prev[c] = 0.0;
+    P.Y[1 * kPM + c] = y1[c];
+  }
   C.kp = 1;
   C.flo = 1;
   C.dlo = 1;
@@ -126,19 +242,21 @@ __device__ inline double pass_bytes(const KParams& P, int kp, int flo) {
 }
 
 // The small exponential and the controller for an attempt with basis size j.
-// Whole workgroup.  Loops while the attempt is rejected at m_max (same basis, smaller tau).
-__device__ inline void attempt_end(const KParams& P, int j, bool breakdown, double* lds) {
-  Ctrl& C = *P.ctrl;
-  __shared__ int s_again;
+// Whole workgroup.  Loops while the attempt is rejected at m_max (same basis,
+// smaller tau).
+__device__ __noinline__ void attempt_end(const KParams& P, SmallState& S, int j, bool breakdown,
+                                         double* lds) {
+  Ctrl& C = S.C;
   const int n = j + 1;
   const int n16 = pad16(n);
+  const uint64_t te0 = (uint64_t)wall_clock64();
   for (int round = 0;; ++round) {
     const double tau = C.tau;
     double* A = P.expm;
     for (int e = threadIdx.x; e < n16 * n16; e += kThreads) {
-      const int r = e / n16, c = e % n16;
+      const int r = e / n16, c = e - r * n16;
       double v = 0.0;
-      if (r < j && c < j) v = tau * Hel(P, r + 1, c + 1);
+      if (r < j && c < j) v = tau * h_get(S, r + 1, c + 1);
       else if (c == j && r == 0) v = tau;
       A[r * kExpmLd + c] = v;
     }
@@ -146,7 +264,7 @@ __device__ inline void attempt_end(const KParams& P, int j, bool breakdown, doub
     const int slot = wg_expm(P.expm, n, lds);
     const double* F = P.expm + (size_t)slot * kExpmSlot;
     if (threadIdx.x == 0) {
-      const double eps = breakdown ? 0.0 : C.beta * fabs(Hel(P, j + 1, j)) * fabs(F[(j - 1) * kExpmLd + j]);
+      const double eps = breakdown ? 0.0 : C.beta * fabs(h_get(S, j + 1, j)) * fabs(F[(j - 1) * kExpmLd + j]);
       CtrlIn ci;
       ci.T_end = C.T_end; ci.tol = C.tol; ci.T_now = C.T_now; ci.tau = tau;
       ci.m_min = C.m_min; ci.m_max = C.m_max; ci.m = C.m; ci.have_old = C.have_old;
@@ -169,7 +287,6 @@ __device__ inline void attempt_end(const KParams& P, int j, bool breakdown, doub
         C.status = KIOPS_ERR_NONFINITE;
         C.phase = kPhaseDone;
       } else if (o.accept) {
-        for (int i = 1; i <= j; ++i) C.cg[i] = C.beta * F[(i - 1) * kExpmLd] * P.sinv[i];
         C.jg = j;
         C.tau_new = o.tau_new;
         C.m_new = o.m_new;
@@ -190,20 +307,30 @@ __device__ inline void attempt_end(const KParams& P, int j, bool breakdown, doub
           C.phase = kPhasePass;
         }
       }
-      s_again = again;
+      S.again = again;
     }
     __syncthreads();
-    if (!s_again) break;
+    if (C.phase == kPhaseGather) {
+      // gather coefficients c_i = beta F(i, 1) / s_{i-1}
+      for (int i = 1 + threadIdx.x; i <= j; i += kThreads) C.cg[i] = C.beta * F[(i - 1) * kExpmLd] * S.sinv[i];
+      __syncthreads();
+    }
+    if (!S.again) break;
   }
+  if (threadIdx.x == 0) C.t_expm += (uint64_t)wall_clock64() - te0;
 }
 
 // Epilogue after the setup phase.
-__device__ inline void epilogue_setup(const KParams& P, double* lds) {
-  reduce_partials(P, kPM, lds);
+__device__ __noinline__ void epilogue_setup(const KParams& P, SmallState& S, double* lds) {
+  reduce_partials(P, S.red, lds);
+  for (int e = threadIdx.x; e < kLdh * (kWinMax + 1); e += kThreads) (&S.Hb[0][0])[e] = 0.0;
+  for (int e = threadIdx.x; e < kRingRows * kWinMax; e += kThreads) (&S.Gw[0][0])[e] = 0.0;
+  for (int e = threadIdx.x; e < kLdh; e += kThreads) S.sinv[e] = 0.0;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    Ctrl& C = *P.ctrl;
+    Ctrl& C = S.C;
     double nb = 0.0;
-    for (int k = 0; k < P.p; ++k) nb = lds[k] > nb ? lds[k] : nb;
+    for (int k = 0; k < P.p; ++k) nb = S.red[k] > nb ? S.red[k] : nb;
     double nu = 1.0, mu = 1.0;
     if (P.p > 0 && nb > 0.0 && isfinite(nb)) {
       int e;
@@ -212,6 +339,10 @@ __device__ inline void epilogue_setup(const KParams& P, double* lds) {
       nu = ldexp(1.0, -c);
       mu = ldexp(1.0, c);
     }
+    const uint64_t tw = C.t_work, tl = C.t_last;
+    C = Ctrl{};
+    C.t_work = tw;
+    C.t_last = tl;
     C.nu = nu; C.mu = mu;
     C.T_now = 0.0; C.T_end = P.T_end; C.tau = P.T_end; C.tol = P.tol;
     C.p = P.p; C.q = P.q; C.m_min = P.m_min; C.m_max = P.m_max; C.max_substeps = P.max_substeps;
@@ -220,10 +351,6 @@ __device__ inline void epilogue_setup(const KParams& P, double* lds) {
     C.m_new = C.m;
     C.status = KIOPS_OK;
     C.mode = P.mode;
-    C.substeps = C.rejections = C.expms = C.breakdowns = C.attempts = 0;
-    C.matvecs = 0;
-    C.last_omega = 0.0;
-    C.beta = 0.0;
     C.alg_bytes = (double)P.p * 8.0 * (double)P.N;   // ||B||_1
     if (!isfinite(nb)) {
       C.status = KIOPS_ERR_NONFINITE;
@@ -231,101 +358,107 @@ __device__ inline void epilogue_setup(const KParams& P, double* lds) {
     } else if (P.T_end == 0.0) {
       C.phase = kPhaseDone;
     } else {
-      start_substep(P);
+      start_substep(P, S);
     }
   }
   __syncthreads();
+  publish(P, S);
 }
 
-// Epilogue after pass kp.
-__device__ inline void epilogue_pass(const KParams& P, double* lds) {
-  Ctrl& C = *P.ctrl;
-  __shared__ int s_action;    // 0 continue, 1 attempt end, 2 attempt end with breakdown
-  __shared__ int s_j;
-  const int kp = C.kp;
-  const int dlo = C.dlo;
-  const int ngd = kp - dlo;
-  reduce_partials(P, kDotSlots, lds);
+// Epilogue after pass kp: Algorithm 2's normalisation of R_kp (its norm is
+// s_{kp-1} = h_{kp,kp-1}), the window coefficients h_{i,kp} by modified
+// Gram-Schmidt (lines 7-10) reproduced from the inner products, the
+// coefficients of the next pass, and the end of an attempt.
+__device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, double* lds) {
+  Ctrl& C = S.C;
+  reduce_partials(P, S.red, lds);
   if (threadIdx.x == 0) {
     int action = 0;
-    const int k = kp;
+    const int k = C.kp;
+    const int dlo = C.dlo;
+    const int ngd = k - dlo;
     const int p = C.p;
-    const double* yk = Yrow(P, k);
+    const double* red = S.red;
+    const double* yk = y_row(S, k);
     double ykr[kPM], Ky[kPM];
 #pragma unroll
-    for (int c = 0; c < kPM; ++c) ykr[c] = (c < p) ? yk[c] : 0.0;
+    for (int c = 0; c < kPM; ++c) ykr[c] = yk[c];
 #pragma unroll
-    for (int c = 0; c < kPM; ++c) Ky[c] = (c + 1 < kPM) ? ykr[c + 1] : 0.0;   // K y: upper shift
-    double RR = lds[kDotRR], UU = lds[kDotUU], Ck = lds[kDotCk];
+    for (int c = 0; c < kPM; ++c) Ky[c] = (c + 1 < kPM && c + 1 < p) ? ykr[c + 1] : 0.0;   // K y
+    double RR = red[kDotRR], UU = red[kDotUU], Ck = red[kDotCk];
 #pragma unroll
     for (int c = 0; c < kPM; ++c) { RR += ykr[c] * ykr[c]; UU += Ky[c] * Ky[c]; Ck += ykr[c] * Ky[c]; }
     C.matvecs += 1;
-    C.alg_bytes += pass_bytes(P, kp, C.flo);
+    C.alg_bytes += pass_bytes(P, k, C.flo);
     bool finite = isfinite(RR) && isfinite(UU) && isfinite(Ck);
-    for (int d = 0; d < ngd; ++d) finite = finite && isfinite(lds[kDotG + d]) && isfinite(lds[kDotC + d]);
+    for (int d = 0; d < ngd; ++d) finite = finite && isfinite(red[kDotG + d]) && isfinite(red[kDotC + d]);
     const double s = sqrt(RR);
     if (!finite) {
       C.status = KIOPS_ERR_NONFINITE;
       C.phase = kPhaseDone;
       action = 3;
     } else if (k == 1 && s == 0.0) {
-      // zero start vector: the solution stays zero (w == 0 already)
-      C.beta = 0.0;
+      C.beta = 0.0;                             // zero start vector: w stays zero
       C.T_now = C.T_end;
       C.phase = kPhaseDone;
       action = 3;
-    } else if (k > 1 && (s == 0.0 || s <= 1e-12 * P.unorm[k - 1])) {
-      Hel(P, k, k - 1) = 0.0;                 // happy breakdown (Alg. 2, lines 12-14)
+    } else if (k > 1 && (s == 0.0 || s <= 1e-12 * S.unorm_prev)) {
+      h_set(S, P, k, k - 1, 0.0);               // happy breakdown (Alg. 2, lines 12-14)
       C.breakdown = 1;
       C.s_last = s;
-      action = 2;
+      action = (C.mode == kModeBasis) ? 3 : 2;
+      if (action == 3) C.phase = kPhaseDone;
     } else {
       if (k == 1) C.beta = s;
-      else Hel(P, k, k - 1) = s;
+      else h_set(S, P, k, k - 1, s);
       C.s_last = s;
       const double si = 1.0 / s;
+      S.sinv[k] = si;
       P.sinv[k] = si;
-      P.unorm[k] = sqrt(UU) * si;
+      S.unorm_prev = sqrt(UU) * si;
+      double* gk = S.Gw[k % kRingRows];
+#pragma unroll
+      for (int d = 0; d < kWinMax; ++d) gk[d] = 0.0;
+      gk[kWinMax - 1] = 1.0;                    // G(k, k)
       for (int d = 0; d < ngd; ++d) {
         const int i = dlo + d;
+        const double* yi = y_row(S, i);
         double yd = 0.0;
-        const double* yi = Yrow(P, i);
 #pragma unroll
-        for (int c = 0; c < kPM; ++c) yd += (c < p) ? yi[c] * ykr[c] : 0.0;
-        const double g = (lds[kDotG + d] + yd) * P.sinv[i] * si;
-        Gel(P, i, k) = g;
-        Gel(P, k, i) = g;
+        for (int c = 0; c < kPM; ++c) yd += yi[c] * ykr[c];
+        gk[i - (k - kWinMax + 1)] = (red[kDotG + d] + yd) * S.sinv[i] * si;
       }
-      Gel(P, k, k) = 1.0;
       // modified Gram-Schmidt over the window [dlo, k] (Alg. 2, lines 7-10)
+      double hk[kWinMax];
       for (int i = dlo; i <= k; ++i) {
         double raw;
         if (i < k) {
-          const double* yi = Yrow(P, i);
+          const double* yi = y_row(S, i);
           double yd = 0.0;
 #pragma unroll
-          for (int c = 0; c < kPM; ++c) yd += (c < p) ? yi[c] * Ky[c] : 0.0;
-          raw = lds[kDotC + (i - dlo)] + yd;
+          for (int c = 0; c < kPM; ++c) yd += yi[c] * Ky[c];
+          raw = red[kDotC + (i - dlo)] + yd;
         } else {
           raw = Ck;
         }
-        double h = raw * P.sinv[i] * si;
-        for (int l = dlo; l < i; ++l) h -= Hel(P, l, k) * Gel(P, i, l);
-        Hel(P, i, k) = h;
+        double h = raw * S.sinv[i] * si;
+        for (int l = dlo; l < i; ++l) h -= hk[l - dlo] * g_get(S, i, l);
+        hk[i - dlo] = h;
+        h_set(S, P, i, k, h);
       }
       // coefficients of the next pass: R_{k+1} = si U_k - sum_i H(i,k) sinv[i] R_i
-      double* yn = Yrow(P, k + 1);
-#pragma unroll
+      double* yn = y_row(S, k + 1);
       for (int c = 0; c < kPM; ++c) {
         double v = (c < p) ? si * Ky[c] : 0.0;
         if (c < p)
-          for (int i = dlo; i <= k; ++i) v -= Hel(P, i, k) * P.sinv[i] * Yrow(P, i)[c];
+          for (int i = dlo; i <= k; ++i) v -= hk[i - dlo] * S.sinv[i] * y_row(S, i)[c];
         yn[c] = (c < p) ? v : 0.0;
+        P.Y[(k + 1) * kPM + c] = yn[c];
         C.yb_prev[c] = (c < p) ? C.nu * ykr[c] : 0.0;
         C.yb_cur[c] = (c < p) ? C.nu * v : 0.0;
       }
       C.a = si;
-      for (int i = dlo; i <= k; ++i) C.bw[i] = -Hel(P, i, k) * P.sinv[i];
+      for (int i = dlo; i <= k; ++i) C.bw[i] = -hk[i - dlo] * S.sinv[i];
       C.flo = dlo;
       C.kp = k + 1;
       C.dlo = (C.q == 0) ? 1 : ((k + 1 - C.q + 1) > 1 ? (k + 1 - C.q + 1) : 1);
@@ -335,21 +468,21 @@ __device__ inline void epilogue_pass(const KParams& P, double* lds) {
       } else if (jdone >= C.m && jdone >= 1) {
         action = 1;
       }
-      C.phase = (action == 3) ? kPhaseDone : kPhasePass;
+      if (action != 3) C.phase = kPhasePass;
     }
-    if (action == 2 && C.mode == kModeBasis) { C.phase = kPhaseDone; action = 3; }
-    s_action = action;
-    s_j = k - 1;
+    S.action = action;
+    S.jj = k - 1;
   }
   __syncthreads();
-  const int action = s_action;
-  if (action == 1 || action == 2) attempt_end(P, s_j, action == 2, lds);
+  const int action = S.action;
+  if (action == 1 || action == 2) attempt_end(P, S, S.jj, action == 2, lds);
+  publish(P, S);
 }
 
 // Epilogue after the gather: advance T_now (Alg. 1, line 24) and start the next substep.
-__device__ inline void epilogue_gather(const KParams& P) {
+__device__ __noinline__ void epilogue_gather(const KParams& P, SmallState& S) {
   if (threadIdx.x == 0) {
-    Ctrl& C = *P.ctrl;
+    Ctrl& C = S.C;
     const double s = P.elem_bytes;
     C.alg_bytes += (8.0 + s * (double)(C.jg - 1) + 8.0) * (double)P.N;
     C.T_now = C.T_now + C.tau;
@@ -364,10 +497,11 @@ __device__ inline void epilogue_gather(const KParams& P) {
       C.status = KIOPS_ERR_NOT_CONVERGED;
       C.phase = kPhaseDone;
     } else {
-      start_substep(P);
+      start_substep(P, S);
     }
   }
   __syncthreads();
+  publish(P, S);
 }
 
 template <typename T>
@@ -411,9 +545,9 @@ __device__ inline void setup_phase(const KParams& P, const Op& op, T* bcopy, dou
   const int64_t gt = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int64_t gs = (int64_t)gridDim.x * kThreads;
   for (int64_t e = gt; e < (int64_t)kLdh * kLdh; e += gs) { P.H[e] = 0.0; P.G[e] = 0.0; }
-  double sums[kPM];
+  double sums[kDotSlots];
 #pragma unroll
-  for (int k = 0; k < kPM; ++k) sums[k] = 0.0;
+  for (int k = 0; k < kDotSlots; ++k) sums[k] = 0.0;
   const bool copy_b0 = P.w != P.b[0];
   for (int64_t n = gt; n < P.N; n += gs) {
     if (copy_b0) P.w[n] = P.b[0][n];
@@ -427,7 +561,7 @@ __device__ inline void setup_phase(const KParams& P, const Op& op, T* bcopy, dou
     }
   }
   op.setup_coefficients(P, gt, gs);
-  block_sum(sums, kPM, lds, P.partials + (int64_t)blockIdx.x * P.ndot_stride);
+  block_sum(sums, kDotSlots, lds, P.partials + (int64_t)blockIdx.x * P.ndot_stride);
 }
 
 // Gather w <- sum_i cg[i] R_i (R_1 = w).
@@ -458,27 +592,38 @@ __device__ inline void gather_phase(const KParams& P, const BasisPtrs<T>& bp, do
   __syncthreads();
 }
 
+// Parameters live in device memory (written by the host before the launch) so
+// that no by-value kernel argument has its address taken.
 template <class Op, typename T>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
-kiops_solve_kernel(KParams P, Op op) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Op::kWavesPerEU, 8)))
+kiops_solve_kernel(const KParams* __restrict__ Pp, const Op* __restrict__ opp) {
+  const KParams& P = *Pp;
+  const Op& op = *opp;
   __shared__ double lds[kLdsDoubles];
   __shared__ PassCtx<T> pctx;
-  const unsigned nwg = gridDim.x;
+  __shared__ SmallState S;       // used by workgroup 0 only
+  __shared__ int s_phase;
   T* bcopy = reinterpret_cast<T*>(P.bcopy);
   BasisPtrs<T> bp;
   bp.R1 = P.mixed ? reinterpret_cast<const T*>(P.slots) : reinterpret_cast<const T*>(P.w);
   bp.slots = reinterpret_cast<T*>(P.slots);
   bp.N = P.N;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S.C.t_work = S.C.t_wait = S.C.t_epi = 0;
+    S.C.t_expm = S.C.t_arrive_max = S.C.t_arrive_mean = S.C.n_barriers = 0;
+    S.C.t_last = (uint64_t)wall_clock64();
+  }
 
+  unsigned epoch = 0;
   setup_phase<Op, T>(P, op, bcopy, lds);
-  grid_barrier(P.bar, nwg, P.spin_limit, [&] { epilogue_setup(P, lds); });
+  grid_barrier(P, S, epoch, [&] { epilogue_setup(P, S, lds); });
 
-  for (int iter = 0;; ++iter) {
+  for (;;) {
     if (aborted(P)) break;
-    __shared__ int s_phase;
     if (threadIdx.x == 0) s_phase = __hip_atomic_load(&P.ctrl->phase, __ATOMIC_RELAXED, KIOPS_AGENT);
     __syncthreads();
     const int phase = s_phase;
+    __syncthreads();
     if (phase == kPhaseDone) break;
     if (phase == kPhasePass) {
       load_pass_ctx<T>(P, pctx);
@@ -487,15 +632,16 @@ kiops_solve_kernel(KParams P, Op op) {
       T* Rout = bp.get_mut(pctx.kp);
       op.pass(pctx, bp, P.w, Rout, acc, reinterpret_cast<T*>(lds));
       store_partials(P, acc, lds);
-      grid_barrier(P.bar, nwg, P.spin_limit, [&] { epilogue_pass(P, lds); });
+      grid_barrier(P, S, epoch, [&] { epilogue_pass(P, S, lds); });
     } else {
       gather_phase<T>(P, bp, lds);
-      grid_barrier(P.bar, nwg, P.spin_limit, [&] { epilogue_gather(P); });
+      grid_barrier(P, S, epoch, [&] { epilogue_gather(P, S); });
     }
   }
 }
 
-__global__ void kiops_reset_kernel(Barrier* b, Ctrl* c) {
+__global__ void kiops_reset_kernel(Barrier* b, Ctrl* c, unsigned* arrive, int nwg) {
+  for (int i = threadIdx.x; i < nwg; i += blockDim.x) arrive[i] = 0u;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     b->count = 0;
     b->gen = 0;
@@ -503,6 +649,8 @@ __global__ void kiops_reset_kernel(Barrier* b, Ctrl* c) {
     b->pad = 0;
     c->phase = kPhaseDone;
     c->status = KIOPS_OK;
+    c->t_work = c->t_wait = c->t_epi = 0;
+    c->t_expm = c->t_arrive_max = c->t_arrive_mean = c->n_barriers = 0;
   }
 }
 
