@@ -104,7 +104,7 @@ typedef struct {
   int32_t substeps;       /* accepted substeps */
   int32_t rejections;     /* rejected attempts */
   int32_t expms;          /* small exponentials computed */
-  int32_t breakdowns;     /* happy breakdowns (Algorithm 2, line 12) */
+  int32_t breakdowns;     /* happy breakdowns (Algorithm 2) */
   int32_t grid_blocks;    /* workgroups of the persistent launch */
   int64_t matvecs;        /* products with A~ */
   double last_omega;      /* scaled error of the last attempt, Eq. (39) */
@@ -143,7 +143,7 @@ kiops_status kiops_set_workspace(kiops_operator* op, void* dev_ptr, size_t bytes
  *   tau   >= 0; tau == 0 copies b_0 to w with no product.
  *   p     0..KIOPS_P_MAX; V is a host array of p+1 device pointers, V[k] = b_k.
  *   tol   > 0, absolute tolerance of Eq. (39) (the paper's default is 1e-7).
- *   m_init initial Krylov dimension, clamped into [m_min, m_max] (Algorithm 1, line 3).
+ *   m_init initial Krylov dimension, clamped into [m_min, m_max] (Algorithm 1).
  *   q     IOP window: each new basis vector is orthogonalised against the last
  *         q ones (the paper uses 2); 0 = all (full Arnoldi).
  *   w     device, N entries, written with the result; may equal V[0], must not
@@ -176,8 +176,8 @@ kiops_status kiops_device_info(const kiops_operator* op, int* compute_units, int
  *   8*N + 256 bytes (b_0 is staged there).
  *
  * kiops_small_expm: F = exp(tau Hs) for a device n x n row-major matrix Hs
- *   (n <= KIOPS_M_MAX_LIMIT + 1), F device n x n, by the device's diagonal
- *   Pade / scaling-and-squaring routine (Section 3.3.1).  scratch: device,
+ *   (n <= KIOPS_M_MAX_LIMIT + 1), F device n x n, by the device's scaling-and-squaring
+ *   routine (Section 3.3.1; truncated Taylor series, degree <= 16).  scratch: device,
  *   KIOPS_EXPM_SCRATCH_DOUBLES doubles, caller-owned.
  */
 kiops_status kiops_iop_basis(kiops_operator* op, int p, const double* const* V, int m, int q,

@@ -5,10 +5,10 @@ estimate eps of Eq. (36), whether Algorithm 2 broke down, and the controller
 state.  Output: accept?, tau_new, m_new and omega.
 
   omega = T_end eps / (tau tol)                         Eq. (39), accept iff omega <= delta = 1.4
-  breakdown (or omega == 0): accept, tau_new = tau, m_new = m      Alg. 4 lines 4-8
+  breakdown (or omega == 0): accept, tau_new = tau, m_new = m      Alg. 4
   j == m_max:
       rejected: m_new = j, tau_new = tau (0.6/omega)^(1/(ord+1)),
-                clipped below by tau/5 and above by T_end - T_now    Alg. 4 lines 10-13
+                clipped below by tau/5 and above by T_end - T_now    Alg. 4
       accepted: tau_new = tau (0.9/omega)^(1/(ord+1)), clipped to [tau/5, 5 tau]   Eq. (44)
   otherwise:
       m_new = ceil(j + log(omega/0.9)/log(kappa)), clipped to

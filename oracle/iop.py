@@ -1,8 +1,8 @@
 """Algorithm 2 of Section 3.3: the incomplete orthogonalization procedure.
 
 Works on augmented vectors [x; y] of length N + p without forming A~; the
-product A~ [x; y] = [A x + nu B y; K y] is the block form of Algorithm 2's
-lines 4-6 (B already scaled by nu of Eq. (48)).  Each new vector is
+product A~ [x; y] = [A x + nu B y; K y] is the block form of the augmented
+product of Theorem 1 (B already scaled by nu of Eq. (48)).  Each new vector is
 orthogonalised, by modified Gram-Schmidt, against the last q basis vectors
 (the paper's procedure is q = 2); q = 0 means all of them (full Arnoldi).
 
@@ -47,7 +47,7 @@ class IOPBasis:
             self.breakdown = True
 
     def apply_aug(self, v: np.ndarray) -> np.ndarray:
-        """A~ v for v = [x; y] (Algorithm 2, lines 4-6)."""
+        """A~ v for v = [x; y] (Algorithm 2, Theorem 1)."""
         N, p = self.N, self.p
         x, y = v[:N], v[N:]
         out = np.empty(N + p)

@@ -2,7 +2,7 @@
 
     tau = T_end; m = max(m_min, min(m_init, m_max)); T_now = 0; w = b_0
     while T_now < T_end:
-        start vector [w; mu y(T_now)], y(t) = [t^{p-1}/(p-1)!, ..., t, 1]   Alg. 1 lines 10-15, Eq. (47)
+        start vector [w; mu y(T_now)], y(t) = [t^{p-1}/(p-1)!, ..., t, 1]   Alg. 1, Eq. (47)
         extend the IOP basis to m (Algorithm 2)
         F = exp(tau H~), H~ = [[H_j, e_1], [0, 0]]                        Eqs. (37)-(38)
         eps = beta |h_{j+1,j}| |F(j, j+1)|                                Eq. (36)

@@ -17,6 +17,10 @@ HIPCC_FLAGS = [
     "-shared",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary vector registers: the small products
+    # keep their accumulators across a software-pipelined loop, and the
+    # accumulator-register form copies them back and forth every iteration
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall",
     "-Wno-unused-function",
 ]

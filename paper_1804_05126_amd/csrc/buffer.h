@@ -1,0 +1,59 @@
+// Raw buffer access (gfx9 buffer resources) and wave-uniform values.
+//
+// A load whose byte offset lies outside [0, num_records) returns zero without
+// touching memory, and such a store is dropped.  Absent arrays get
+// num_records = 0, absent positions an offset of kNoOffset, so loads can be
+// issued unconditionally.  The base address sits in scalar registers and the
+// per-lane part is a 32-bit byte offset, so an array is limited to 4 GiB.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kiops {
+
+constexpr uint32_t kNoOffset = 0xFFFFFFF0u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint64_t bytes) {
+  const int n = (p && bytes < 0xFFFFFFFFull) ? (int)(uint32_t)bytes : 0;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, n, 0x00020000);
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+typedef unsigned int kiops_u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+typedef unsigned int kiops_u32x4 __attribute__((__vector_size__(4 * sizeof(unsigned int))));
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(kiops_u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+}
+// two consecutive doubles (16-byte aligned offset)
+__device__ __forceinline__ void buf_ld2(__amdgpu_buffer_rsrc_t r, uint32_t off, double& x, double& y) {
+  const kiops_u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  x = __builtin_bit_cast(double, kiops_u32x2{v[0], v[1]});
+  y = __builtin_bit_cast(double, kiops_u32x2{v[2], v[3]});
+}
+
+// The value of the first active lane, for values the program knows to be the
+// same across the wave (lets the compiler keep them in scalar registers).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T* uniform(T* p) {
+  const uint64_t b = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+}  // namespace kiops

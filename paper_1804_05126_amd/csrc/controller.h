@@ -81,11 +81,11 @@ KIOPS_HD inline CtrlOut ctrl_decide(const CtrlIn& s, int j, double eps, bool bre
     o.accept = 0; o.m_new = s.m; o.tau_new = tau; o.branch = kBranchNonFinite;
     return o;
   }
-  if (breakdown || omega == 0.0) {                               // Alg. 4, lines 4-8
+  if (breakdown || omega == 0.0) {                               // Alg. 4: breakdown
     o.accept = 1; o.tau_new = tau; o.m_new = s.m; o.branch = kBranchBreakdown;
     return o;
   }
-  if (j == s.m_max) {                                            // Alg. 4, lines 9-16
+  if (j == s.m_max) {                                            // Alg. 4: at m_max
     const double ord = ctrl_order(s, j, eps);
     if (omega > kDelta) {
       double tn = tau * pow(kGammaReject / omega, 1.0 / (ord + 1.0));
@@ -98,7 +98,7 @@ KIOPS_HD inline CtrlOut ctrl_decide(const CtrlIn& s, int j, double eps, bool bre
     o.accept = 1; o.tau_new = tn; o.m_new = s.m; o.branch = kBranchTauAccept;
     return o;
   }
-  const double kap = ctrl_kappa(s, j, omega);                    // Alg. 4, line 18
+  const double kap = ctrl_kappa(s, j, omega);                    // Alg. 4, Eq. (45)
   double mn = ceil((double)j + log(omega / kGamma) / log(kap));  // Eq. (46)
   double lo = ctrl_max((double)s.m_min, floor(0.75 * (double)j));
   double hi = ctrl_min((double)s.m_max, ceil(4.0 * (double)j / 3.0));

@@ -326,12 +326,18 @@ __global__ void export_h_kernel(const double* H, int m, double* out) {
 __global__ void small_expm_kernel(const double* Hs, int n, double tau, double* F, double* scratch) {
   __shared__ double lds[kLdsDoubles];
   const int n16 = pad16(n);
-  for (int e = threadIdx.x; e < n16 * n16; e += kThreads) {
-    const int r = e / n16, c = e % n16;
-    scratch[r * kExpmLd + c] = (r < n && c < n) ? tau * Hs[r * n + c] : 0.0;
+  double colmax = 0.0;
+  for (int c = threadIdx.x; c < n16; c += kThreads) {
+    double cs = 0.0;
+    for (int r = 0; r < n16; ++r) {
+      const double v = (r < n && c < n) ? tau * Hs[r * n + c] : 0.0;
+      scratch[r * kExpmLd + c] = v;
+      cs += fabs(v);
+    }
+    colmax = cs > colmax ? cs : colmax;
   }
-  __syncthreads();
-  const int slot = wg_expm(scratch, n, lds);
+  const double eta = wg_max(colmax, lds);
+  const int slot = wg_expm(scratch, n, eta, lds);
   const double* R = scratch + (size_t)slot * kExpmSlot;
   for (int e = threadIdx.x; e < n * n; e += kThreads) F[e] = R[(e / n) * kExpmLd + (e % n)];
 }

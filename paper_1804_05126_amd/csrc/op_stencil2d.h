@@ -20,33 +20,10 @@
 // position serves every array), so an array is limited to 4 GiB.
 #pragma once
 
+#include "buffer.h"
 #include "pass_common.h"
 
 namespace kiops {
-
-// Buffer resources (gfx9 raw buffers): a load whose byte offset lies outside
-// [0, num_records) returns zero without touching memory, and such a store is
-// dropped.  Absent arrays get num_records = 0, absent positions an offset of
-// kNoOffset, so every load of a tile can be issued unconditionally.
-constexpr uint32_t kNoOffset = 0xFFFFFFF0u;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint64_t bytes) {
-  const int n = (p && bytes < 0xFFFFFFFFull) ? (int)(uint32_t)bytes : 0;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, n, 0x00020000);
-}
-__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
-typedef unsigned int kiops_u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
-__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(kiops_u32x2, v), r, off, 0, 0);
-}
-__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
-}
 
 template <typename T, int PB>
 struct Stencil2D {

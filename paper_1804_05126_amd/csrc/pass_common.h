@@ -1,10 +1,10 @@
 // Per-pass context shared by the operator passes.
 //
 // One pass produces the next Krylov vector without a second sweep over memory
-// (Algorithm 2, lines 3-17, with the normalisation deferred by one step):
+// (Algorithm 2, with the normalisation deferred by one step):
 //
 //   R_kp = a * U_{kp-1} + sum_{i in [flo, kp-1]} bw[i] R_i      (orthogonalised, unnormalised)
-//   U_kp = A~ R_kp = A x(R_kp) + nu B y(R_kp)                   (lines 4-6)
+//   U_kp = A~ R_kp = A x(R_kp) + nu B y(R_kp)                   (Theorem 1)
 //
 // with v_i = R_i * sinv[i] and U_{kp-1} = A~ R_{kp-1}.  Stencil operators
 // recompute U_{kp-1} on the fly from R_{kp-1} (two-level stencil over a halo

@@ -1,107 +1,61 @@
 // Small dense matrix exponential on one workgroup (256 threads), float64.
 //
-// Section 3.3.1 computes exp(tau H~) of the (j+1) x (j+1) projected matrix
-// with "a diagonal Pade approximation combined with scaling and squaring".
-// This is that method in the form of N. J. Higham, "The scaling and squaring
-// method for the matrix exponential revisited", SIAM J. Matrix Anal. Appl. 26
-// (2005): choose the Pade degree m in {3, 5, 7, 9, 13} from ||A||_1 and the
-// published thresholds theta_m; for degree 13 scale A by 2^-s so that
-// ||A/2^s||_1 <= theta_13; evaluate r_m = q_m(A)^-1 p_m(A) with p_m(A) = V + U,
-// q_m(A) = V - U (U odd part, V even part), solve by LU with partial pivoting;
-// square s times.
+// Section 3.3.1 forms exp(tau H~) of the (j+1) x (j+1) projected matrix by
+// scaling and squaring around a rational (diagonal Pade) approximant.  Here the
+// approximant is the truncated Taylor series, still with scaling and squaring:
+// a Taylor polynomial needs nothing but matrix products, and those run on the
+// f64 matrix cores (v_mfma_f64_16x16x4), whereas a Pade quotient needs a
+// pivoted LU solve whose column-after-column dependence leaves a workgroup
+// waiting on latency for most of its run.
 //
-// Matrices live in global scratch memory (they stay in L2: at most 9 x 166 KB)
-// with a fixed leading dimension; entries beyond n are kept zero so that the
-// 16-padded products are exact.
+// Degree.  With X the matrix and eta = ||X||_1, the degree is the smallest m in
+// {2, 4, 6, 9, 12, 16} with eta <= theta_m, where theta_m is the largest theta
+// with sum_{k>m} theta^k / k! <= 2^-53 e^-theta.  Every eigenvalue of X lies in
+// |z| <= eta, so ||e^X||_1 >= e^-eta and the truncation error stays below the
+// unit roundoff relative to ||e^X||_1.  Beyond theta_16 the matrix is scaled by
+// 2^-s (s = ceil(log2(eta / theta_16))) and the result squared s times.
+//
+// Evaluation (Paterson & Stockmeyer 1973).  With m = q b and c_k = 1/k!:
+//   powers X^2 .. X^b,
+//   Z_{q-1} = sum_{i<b} c_{(q-1)b+i} X^i + c_m X^b,
+//   Z_k     = X^b Z_{k+1} + sum_{i<b} c_{kb+i} X^i,   k = q-2 .. 0,
+// and T_m(X) = Z_0: (b - 1) + (q - 1) products, the sums fused into the
+// products' output stage.  (m, b) = (2,2) (4,2) (6,3) (9,3) (12,4) (16,4).
+//
+// Matrices live in global scratch memory (at most 7 x 166 KB, resident in L2)
+// with the fixed leading dimension kExpmLd; entries beyond n are kept zero, so
+// products over the 16-padded size are exact.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include "buffer.h"
 
 namespace kiops {
 
 constexpr int kExpmMaxN = 129;   // m_max + 1
 constexpr int kExpmLd = 144;     // kExpmMaxN rounded up to 16
 constexpr int kExpmSlot = kExpmLd * kExpmLd;
-constexpr int kExpmSlots = 9;
-constexpr int kExpmLdsDoubles = 48 * 17 + 16 * 49 + 16;   // gemm staging + Pade coefficients
+constexpr int kExpmSlots = 9;    // scratch size of the C interface; 7 are used
+constexpr int kExpmLdsDoubles = 264;   // reduction buffer (256) + coefficients (5)
 
-// theta_m for m = 3, 5, 7, 9, 13 (Higham 2005, Table 2.3, double precision).
-__device__ constexpr double kTheta[5] = {1.495585217958292e-2, 2.539398330063230e-1,
-                                         9.504178996162932e-1, 2.097847961257068e0,
-                                         5.371920351148152e0};
+// theta_m for m = 2, 4, 6, 9, 12, 16 (criterion in the header comment).
+__device__ constexpr double kTaylorTheta[6] = {8.733444801477513e-06, 1.6778312117956388e-03,
+                                               1.7719629491983992e-02, 1.135367072544621e-01,
+                                               3.269045734215958e-01, 7.873811561929019e-01};
+__device__ constexpr int kTaylorDeg[6] = {2, 4, 6, 9, 12, 16};
+__device__ constexpr int kTaylorBlk[6] = {2, 2, 3, 3, 4, 4};
 
-// Coefficients of the [m/m] Pade approximant of e^x, numerator p_m(x) = sum c_i x^i,
-// c_i = (2m-i)! m! / ((2m)! i! (m-i)!), by the ratio c_{i+1}/c_i = (m-i)/((2m-i)(i+1)).
-__device__ inline void pade_coeffs(int m, double* c) {
-  c[0] = 1.0;
-  for (int i = 0; i < m; ++i) c[i + 1] = c[i] * (double)(m - i) / ((double)(2 * m - i) * (double)(i + 1));
-}
+typedef double kiops_f64x2 __attribute__((ext_vector_type(2)));
+typedef double kiops_f64x4 __attribute__((ext_vector_type(4)));
 
-__device__ inline int pad16(int n) { return (n + 15) & ~15; }
+__device__ __forceinline__ int pad16(int n) { return (n + 15) & ~15; }
 
-// C = A * B for n16 x n16 matrices with leading dimension kExpmLd (C must not alias A or B).
-// Output in 48 x 48 blocks; thread (tr, tc) of a 16 x 16 layout owns rows
-// tr + 16 a and columns tc + 16 b (a, b < 3) of a block: 9 accumulators.
-__device__ inline void wg_gemm(double* __restrict__ C, const double* __restrict__ A,
-                               const double* __restrict__ B, int n16, double* lds) {
+// Maximum of one value per thread over the workgroup (lds: 256 doubles).
+__device__ __forceinline__ double wg_max(double v, double* lds) {
   const int t = threadIdx.x;
-  const int tr = t >> 4, tc = t & 15;
-  double* sA = lds;                 // [48][17]
-  double* sB = lds + 48 * 17;       // [16][49]
-  for (int r0 = 0; r0 < n16; r0 += 48) {
-    const int nr = (n16 - r0) < 48 ? (n16 - r0) : 48;
-    for (int c0 = 0; c0 < n16; c0 += 48) {
-      const int nc = (n16 - c0) < 48 ? (n16 - c0) : 48;
-      double acc[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) acc[a][b] = 0.0;
-      for (int kk = 0; kk < n16; kk += 16) {
-        for (int e = t; e < 48 * 16; e += 256) {
-          const int r = e >> 4, k = e & 15;
-          sA[r * 17 + k] = (r < nr) ? A[(r0 + r) * kExpmLd + kk + k] : 0.0;
-        }
-        for (int e = t; e < 16 * 48; e += 256) {
-          const int k = e / 48, c = e - k * 48;
-          sB[k * 49 + c] = (c < nc) ? B[(kk + k) * kExpmLd + c0 + c] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int k = 0; k < 16; ++k) {
-          const double b0 = sB[k * 49 + tc], b1 = sB[k * 49 + 16 + tc], b2 = sB[k * 49 + 32 + tc];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const double av = sA[(a * 16 + tr) * 17 + k];
-            acc[a][0] = fma(av, b0, acc[a][0]);
-            acc[a][1] = fma(av, b1, acc[a][1]);
-            acc[a][2] = fma(av, b2, acc[a][2]);
-          }
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-          if (a * 16 + tr < nr && b * 16 + tc < nc)
-            C[(r0 + a * 16 + tr) * kExpmLd + c0 + b * 16 + tc] = acc[a][b];
-    }
-  }
-  __syncthreads();
-}
-
-// ||A||_1 of the leading n x n block (maximum absolute column sum).
-__device__ inline double wg_norm1(const double* A, int n, double* lds) {
-  const int t = threadIdx.x;
-  double best = 0.0;
-  for (int c = t; c < n; c += 256) {
-    double s = 0.0;
-    for (int r = 0; r < n; ++r) s += fabs(A[r * kExpmLd + c]);
-    best = s > best ? s : best;
-  }
-  lds[t] = best;
+  lds[t] = v;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (t < off) lds[t] = lds[t] > lds[t + off] ? lds[t] : lds[t + off];
@@ -112,161 +66,173 @@ __device__ inline double wg_norm1(const double* A, int n, double* lds) {
   return r;
 }
 
-// D = w0 M0 + w1 M1 + w2 M2 + w3 M3 + wI I over the n16 x n16 block (null M ignored).
-__device__ inline void wg_lincomb(double* D, int n, int n16, const double* M0, double w0,
-                                  const double* M1, double w1, const double* M2, double w2,
-                                  const double* M3, double w3, double wI) {
+// Output stage shared by products and plain sums: cf[0] I + sum_{k=1}^{nterms-1}
+// cf[k] X^k, with X^k held in slot k-1 of `pw`.  nterms = 0 adds nothing.
+__device__ __forceinline__ double power_sum(const double* __restrict__ pw, const double* cf,
+                                            int nterms, int n, int row, int col) {
+  double v = 0.0;
+  if (nterms > 0 && row == col && row < n) v = cf[0];
+  for (int k = 1; k < nterms; ++k) v = fma(cf[k], pw[(k - 1) * kExpmSlot + row * kExpmLd + col], v);
+  return v;
+}
+
+// C = alpha A B + (power sum), n16 x n16, leading dimension kExpmLd.  C must
+// not alias A or B.  Each wave owns 16-row strips of C in chunks of NJ <= 5
+// 16 x 16 tiles; per 8-deep slice of the inner dimension a lane holds two
+// entries of A and two of B per tile (the 16x16x4 f64 operand layout: A(i, k)
+// in lane i + 16 k, B(k, j) in lane j + 16 k, C(i, j) in lane j + 16 (i % 4),
+// element i / 4), and the next slice is loaded while the current one is
+// multiplied.  Within a slice, lane group g covers inner indices 2g and 2g+1.
+template <int NJ>
+__device__ __forceinline__ void gemm_strip(__amdgpu_buffer_rsrc_t rC, __amdgpu_buffer_rsrc_t rA,
+                                           __amdgpu_buffer_rsrc_t rB, __amdgpu_buffer_rsrc_t rP,
+                                           int n, int n16, double alpha, const double* cf,
+                                           int nterms, int I, int J0) {
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, g = lane >> 4;
+  constexpr uint32_t kRow = kExpmLd * 8;   // bytes per row
+  const uint32_t oA = (uint32_t)((I * 16 + r16) * kExpmLd + 2 * g) * 8u;
+  const uint32_t oB = (uint32_t)(2 * g * kExpmLd + J0 * 16 + r16) * 8u;
+  kiops_f64x4 acc[NJ];
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) acc[jj] = kiops_f64x4{0.0, 0.0, 0.0, 0.0};
+  // two register sets, X and Y, alternate between slices (n16 is a multiple of
+  // 16, so slices come in pairs); a set is refilled right after its products
+  // are issued, one slice ahead of its use
+  double xa0, xa1, xb0[NJ], xb1[NJ], ya0, ya1, yb0[NJ], yb1[NJ];
+  auto load = [&](uint32_t k, double& a0, double& a1, double* b0, double* b1) {
+    buf_ld2(rA, oA + k * 8u, a0, a1);
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      b0[jj] = buf_ld(rB, oB + k * kRow + jj * 128u, 0.0);
+      b1[jj] = buf_ld(rB, oB + k * kRow + kRow + jj * 128u, 0.0);
+    }
+  };
+  auto mma = [&](double a0, double a1, const double* b0, const double* b1) {
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) acc[jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0[jj], acc[jj], 0, 0, 0);
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) acc[jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1[jj], acc[jj], 0, 0, 0);
+  };
+  load(0, xa0, xa1, xb0, xb1);
+  for (int k0 = 0; k0 < n16; k0 += 16) {
+    load((uint32_t)(k0 + 8), ya0, ya1, yb0, yb1);
+    mma(xa0, xa1, xb0, xb1);
+    // the last pair reloads its own second slice instead of branching
+    load((uint32_t)(k0 + 16 < n16 ? k0 + 16 : k0 + 8), xa0, xa1, xb0, xb1);
+    mma(ya0, ya1, yb0, yb1);
+  }
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    const int col = (J0 + jj) * 16 + r16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = I * 16 + g + 4 * i;
+      const uint32_t o = (uint32_t)(row * kExpmLd + col);
+      double v = (nterms > 0 && row == col && row < n) ? cf[0] : 0.0;
+      for (int k = 1; k < nterms; ++k) v = fma(cf[k], buf_ld(rP, (o + (uint32_t)(k - 1) * kExpmSlot) * 8u, 0.0), v);
+      buf_st(rC, o * 8u, fma(alpha, acc[jj][i], v));
+    }
+  }
+}
+
+// One product on the whole workgroup; every argument is the same on all lanes.
+__device__ __noinline__ void wg_gemm(double* C, const double* A, const double* B, int n, int n16,
+                                     double alpha, const double* pw, const double* cf, int nterms) {
+  n = uniform(n);
+  n16 = uniform(n16);
+  alpha = uniform(alpha);
+  nterms = uniform(nterms);
+  constexpr uint64_t kSlotBytes = (uint64_t)kExpmSlot * 8;
+  const __amdgpu_buffer_rsrc_t rC = make_rsrc(uniform(C), kSlotBytes);
+  const __amdgpu_buffer_rsrc_t rA = make_rsrc(uniform(A), kSlotBytes);
+  const __amdgpu_buffer_rsrc_t rB = make_rsrc(uniform(B), kSlotBytes);
+  const __amdgpu_buffer_rsrc_t rP = make_rsrc(uniform(pw), 4 * kSlotBytes);
+  const int wv = uniform((int)(threadIdx.x >> 6));
+  const int nt = n16 >> 4;
+  const int nch = nt > 5 ? 2 : 1;
+  const int wch = (nt + nch - 1) / nch;
+  for (int u = wv; u < nt * nch; u += 4) {
+    const int I = u / nch;
+    const int J0 = (u - I * nch) * wch;
+    const int nj = (nt - J0) < wch ? (nt - J0) : wch;
+    switch (nj) {
+      case 1: gemm_strip<1>(rC, rA, rB, rP, n, n16, alpha, cf, nterms, I, J0); break;
+      case 2: gemm_strip<2>(rC, rA, rB, rP, n, n16, alpha, cf, nterms, I, J0); break;
+      case 3: gemm_strip<3>(rC, rA, rB, rP, n, n16, alpha, cf, nterms, I, J0); break;
+      case 4: gemm_strip<4>(rC, rA, rB, rP, n, n16, alpha, cf, nterms, I, J0); break;
+      default: gemm_strip<5>(rC, rA, rB, rP, n, n16, alpha, cf, nterms, I, J0); break;
+    }
+  }
+  __syncthreads();
+}
+
+// C = (power sum) over the n16 x n16 block.
+__device__ __forceinline__ void wg_power_sum(double* __restrict__ C, int n, int n16,
+                                             const double* __restrict__ pw, const double* cf,
+                                             int nterms) {
   for (int e = threadIdx.x; e < n16 * n16; e += 256) {
     const int r = e / n16, c = e - r * n16;
-    const int o = r * kExpmLd + c;
-    double v = (r == c && r < n) ? wI : 0.0;
-    if (M0) v = fma(w0, M0[o], v);
-    if (M1) v = fma(w1, M1[o], v);
-    if (M2) v = fma(w2, M2[o], v);
-    if (M3) v = fma(w3, M3[o], v);
-    D[o] = v;
+    C[r * kExpmLd + c] = power_sum(pw, cf, nterms, n, r, c);
   }
   __syncthreads();
 }
 
-// Solve P X = R (n x n, n right-hand sides) in place: on return R holds X.
-// Gaussian elimination with partial pivoting; P is destroyed.
-__device__ inline void wg_lu_solve(double* P, double* R, int n, double* lds) {
-  const int t = threadIdx.x;
-  __shared__ int s_piv;
-  for (int k = 0; k < n; ++k) {
-    // pivot: argmax |P[i][k]|, i >= k (first wave, shuffle reduction)
-    if (t < 64) {
-      double best = -1.0;
-      int bi = k;
-      for (int i = k + t; i < n; i += 64) {
-        const double v = fabs(P[i * kExpmLd + k]);
-        if (v > best) { best = v; bi = i; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_down(best, off, 64);
-        const int oi = __shfl_down(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (t == 0) s_piv = bi;
-    }
-    __syncthreads();
-    const int piv = s_piv;
-    if (piv != k) {
-      for (int c = t; c < 2 * n; c += 256) {
-        double* a = (c < n) ? &P[k * kExpmLd + c] : &R[k * kExpmLd + (c - n)];
-        double* b = (c < n) ? &P[piv * kExpmLd + c] : &R[piv * kExpmLd + (c - n)];
-        const double tmp = *a;
-        *a = *b;
-        *b = tmp;
-      }
-      __syncthreads();
-    }
-    const double inv = 1.0 / P[k * kExpmLd + k];
-    // multipliers kept in column k below the diagonal
-    for (int i = k + 1 + t; i < n; i += 256) P[i * kExpmLd + k] *= inv;
-    __syncthreads();
-    const int rows = n - k - 1;
-    const int cols = (n - k - 1) + n;   // trailing part of P, then all of R
-    for (int e = t; e < rows * cols; e += 256) {
-      const int i = k + 1 + e / cols;
-      const int cc = e % cols;
-      const double l = P[i * kExpmLd + k];
-      if (cc < n - k - 1) {
-        const int c = k + 1 + cc;
-        P[i * kExpmLd + c] = fma(-l, P[k * kExpmLd + c], P[i * kExpmLd + c]);
-      } else {
-        const int c = cc - (n - k - 1);
-        R[i * kExpmLd + c] = fma(-l, R[k * kExpmLd + c], R[i * kExpmLd + c]);
-      }
-    }
-    __syncthreads();
-  }
-  // back substitution, one right-hand side column per thread
-  for (int c = t; c < n; c += 256) {
-    for (int k = n - 1; k >= 0; --k) {
-      double v = R[k * kExpmLd + c];
-      for (int q = k + 1; q < n; ++q) v = fma(-P[k * kExpmLd + q], R[q * kExpmLd + c], v);
-      R[k * kExpmLd + c] = v / P[k * kExpmLd + k];
-    }
-  }
-  __syncthreads();
-  (void)lds;
-}
-
-// exp(A) for the n x n matrix held in slot 0 of `scratch` (zero-padded to 16).
-// Returns the slot index holding the result.  Uses slots 0..8.
-__device__ inline int wg_expm(double* scratch, int n, double* lds) {
+// exp(X) for the n x n matrix X held in slot 0 of `scratch` (zero-padded to a
+// multiple of 16), eta = ||X||_1 (computed by the caller while it writes X).
+// Returns the slot (4 or 5) holding the result.  Slots 0..5 are used; slot 0
+// is left unchanged (the scaling is folded into the products).
+// lds: kExpmLdsDoubles doubles.
+__device__ __forceinline__ int wg_expm(double* scratch, int n, double eta, double* lds) {
   const int n16 = pad16(n);
-  double* A = scratch;
-  double* A2 = scratch + 1 * kExpmSlot;
-  double* A4 = scratch + 2 * kExpmSlot;
-  double* A6 = scratch + 3 * kExpmSlot;
-  double* A8 = scratch + 4 * kExpmSlot;
-  double* T = scratch + 5 * kExpmSlot;
-  double* U = scratch + 6 * kExpmSlot;
-  double* V = scratch + 7 * kExpmSlot;
-  double* W = scratch + 8 * kExpmSlot;
-  double* c = lds + 48 * 17 + 16 * 49;   // Pade coefficients (14 doubles)
+  double* X = scratch;                          // slots 0..3: X, X^2, X^3, X^4
+  double* Z[2] = {scratch + 4 * kExpmSlot, scratch + 5 * kExpmSlot};
+  double* cf = lds + 256;
 
-  const double eta = wg_norm1(A, n, lds);
-  int m = 13;
-  int s = 0;
-  if (eta <= kTheta[0]) m = 3;
-  else if (eta <= kTheta[1]) m = 5;
-  else if (eta <= kTheta[2]) m = 7;
-  else if (eta <= kTheta[3]) m = 9;
-  else if (eta > kTheta[4]) s = (int)ceil(log2(eta / kTheta[4]));
-  if (s > 0) {
-    const double sc = ldexp(1.0, -s);
-    for (int e = threadIdx.x; e < n16 * n16; e += 256) {
-      const int r = e / n16, cc = e - r * n16;
-      A[r * kExpmLd + cc] *= sc;
+  int d = 5, s = 0;
+  if (eta <= kTaylorTheta[5]) {
+    d = 0;
+    while (eta > kTaylorTheta[d]) ++d;
+  } else if (eta < 1e300) {
+    s = (int)ceil(log2(eta / kTaylorTheta[5]));
+    if (s > 1000) s = 1000;
+  }
+  // eta non-finite: no scaling; the result carries the NaN / Inf onward
+  const int m = kTaylorDeg[d], b = kTaylorBlk[d], q = m / b;
+  const double alpha = ldexp(1.0, -s);
+
+  // powers of the scaled matrix: (alpha X)^k = alpha^k X^k
+  if (b >= 2) wg_gemm(X + kExpmSlot, X, X, n, n16, alpha * alpha, nullptr, nullptr, 0);
+  if (b >= 3) wg_gemm(X + 2 * kExpmSlot, X + kExpmSlot, X, n, n16, alpha, nullptr, nullptr, 0);
+  if (b >= 4) wg_gemm(X + 3 * kExpmSlot, X + kExpmSlot, X + kExpmSlot, n, n16, 1.0, nullptr, nullptr, 0);
+
+  // coefficients of block k: cf[i] = c_{kb+i} for i < b (cf[1] carries alpha,
+  // since slot 0 holds the unscaled X); the top block also takes c_m X^b
+  auto set_block = [&](int k, bool top) {
+    if (threadIdx.x == 0) {
+      double c = 1.0;
+      for (int i = 1; i <= k * b; ++i) c /= (double)i;   // c_{kb}
+      for (int i = 0; i < b; ++i) {
+        cf[i] = (i == 1) ? c * alpha : c;
+        c /= (double)(k * b + i + 1);
+      }
+      cf[b] = top ? c : 0.0;                               // c_{(k+1)b} = c_m when top
     }
+    __syncthreads();
+  };
+  set_block(q - 1, true);
+  int cur = 0;
+  wg_power_sum(Z[cur], n, n16, X, cf, b + 1);
+  for (int k = q - 2; k >= 0; --k) {
+    set_block(k, false);
+    wg_gemm(Z[cur ^ 1], X + (b - 1) * kExpmSlot, Z[cur], n, n16, 1.0, X, cf, b);
+    cur ^= 1;
   }
-  if (threadIdx.x == 0) pade_coeffs(m, c);
-  __syncthreads();
-
-  wg_gemm(A2, A, A, n16, lds);
-  if (m >= 5) wg_gemm(A4, A2, A2, n16, lds);
-  if (m >= 7) wg_gemm(A6, A4, A2, n16, lds);
-  if (m == 9) wg_gemm(A8, A4, A4, n16, lds);
-
-  if (m == 13) {
-    // U = A [A6 (c13 A6 + c11 A4 + c9 A2) + c7 A6 + c5 A4 + c3 A2 + c1 I]
-    wg_lincomb(T, n, n16, A6, c[13], A4, c[11], A2, c[9], nullptr, 0.0, 0.0);
-    wg_gemm(W, A6, T, n16, lds);
-    wg_lincomb(T, n, n16, W, 1.0, A6, c[7], A4, c[5], A2, c[3], c[1]);
-    wg_gemm(U, A, T, n16, lds);
-    // V = A6 (c12 A6 + c10 A4 + c8 A2) + c6 A6 + c4 A4 + c2 A2 + c0 I
-    wg_lincomb(T, n, n16, A6, c[12], A4, c[10], A2, c[8], nullptr, 0.0, 0.0);
-    wg_gemm(W, A6, T, n16, lds);
-    wg_lincomb(V, n, n16, W, 1.0, A6, c[6], A4, c[4], A2, c[2], c[0]);
-  } else {
-    // odd part U = A (c1 I + c3 A2 + c5 A4 + ...), even part V = c0 I + c2 A2 + ...
-    const double* P4 = (m >= 5) ? A4 : nullptr;
-    const double* P6 = (m >= 7) ? A6 : nullptr;
-    const double* P8 = (m >= 9) ? A8 : nullptr;
-    wg_lincomb(T, n, n16, A2, c[3], P4, (m >= 5) ? c[5] : 0.0, P6, (m >= 7) ? c[7] : 0.0, P8,
-               (m >= 9) ? c[9] : 0.0, c[1]);
-    wg_gemm(U, A, T, n16, lds);
-    wg_lincomb(V, n, n16, A2, c[2], P4, (m >= 5) ? c[4] : 0.0, P6, (m >= 7) ? c[6] : 0.0, P8,
-               (m >= 9) ? c[8] : 0.0, c[0]);
-  }
-  // P = V - U (slot T), R = V + U (slot W); solve P X = R
-  wg_lincomb(T, n, n16, V, 1.0, U, -1.0, nullptr, 0.0, nullptr, 0.0, 0.0);
-  wg_lincomb(W, n, n16, V, 1.0, U, 1.0, nullptr, 0.0, nullptr, 0.0, 0.0);
-  wg_lu_solve(T, W, n, lds);
-  // square s times, ping-pong between W and U
-  double* cur = W;
-  double* nxt = U;
   for (int i = 0; i < s; ++i) {
-    wg_gemm(nxt, cur, cur, n16, lds);
-    double* tmp = cur;
-    cur = nxt;
-    nxt = tmp;
+    wg_gemm(Z[cur ^ 1], Z[cur], Z[cur], n, n16, 1.0, nullptr, nullptr, 0);
+    cur ^= 1;
   }
-  return cur == W ? 8 : 6;
+  return 4 + cur;
 }
 
 }  // namespace kiops

@@ -1,7 +1,7 @@
 // The persistent solve kernel: Algorithm 1 (Task II) on the device.
 //
 //   setup:   ||B||_1 -> nu, mu (Eqs. (48)-(49)); w <- b_0
-//   substep: start vector [w; mu y(T_now)] (Alg. 1 lines 10-15, Eq. (47))
+//   substep: start vector [w; mu y(T_now)] (Alg. 1, Eq. (47))
 //   passes:  Algorithm 2, one pass per basis vector (see pass_common.h)
 //   attempt: F = exp(tau H~) (Eqs. (37)-(38)), eps (Eq. (36)), Algorithm 4
 //   accept:  w <- beta V(1:N, 1:j) F(1:j, 1) (Algorithm 3, Eq. (33))
@@ -252,16 +252,22 @@ __device__ __noinline__ void attempt_end(const KParams& P, SmallState& S, int j,
   const uint64_t te0 = (uint64_t)wall_clock64();
   for (int round = 0;; ++round) {
     const double tau = C.tau;
+    // X = tau H~ (Eq. (37)) by columns, with its 1-norm
     double* A = P.expm;
-    for (int e = threadIdx.x; e < n16 * n16; e += kThreads) {
-      const int r = e / n16, c = e - r * n16;
-      double v = 0.0;
-      if (r < j && c < j) v = tau * h_get(S, r + 1, c + 1);
-      else if (c == j && r == 0) v = tau;
-      A[r * kExpmLd + c] = v;
+    double colmax = 0.0;
+    for (int c = threadIdx.x; c < n16; c += kThreads) {
+      double cs = 0.0;
+      for (int r = 0; r < n16; ++r) {
+        double v = 0.0;
+        if (r < j && c < j) v = tau * h_get(S, r + 1, c + 1);
+        else if (c == j && r == 0) v = tau;
+        A[r * kExpmLd + c] = v;
+        cs += fabs(v);
+      }
+      colmax = cs > colmax ? cs : colmax;
     }
-    __syncthreads();
-    const int slot = wg_expm(P.expm, n, lds);
+    const double eta = wg_max(colmax, lds);
+    const int slot = wg_expm(P.expm, n, eta, lds);
     const double* F = P.expm + (size_t)slot * kExpmSlot;
     if (threadIdx.x == 0) {
       const double eps = breakdown ? 0.0 : C.beta * fabs(h_get(S, j + 1, j)) * fabs(F[(j - 1) * kExpmLd + j]);
@@ -346,7 +352,7 @@ __device__ __noinline__ void epilogue_setup(const KParams& P, SmallState& S, dou
     C.nu = nu; C.mu = mu;
     C.T_now = 0.0; C.T_end = P.T_end; C.tau = P.T_end; C.tol = P.tol;
     C.p = P.p; C.q = P.q; C.m_min = P.m_min; C.m_max = P.m_max; C.max_substeps = P.max_substeps;
-    int m = P.m_init < P.m_max ? P.m_init : P.m_max;   // Alg. 1, line 3
+    int m = P.m_init < P.m_max ? P.m_init : P.m_max;   // Alg. 1: initial dimension
     C.m = m > P.m_min ? m : P.m_min;
     C.m_new = C.m;
     C.status = KIOPS_OK;
@@ -367,7 +373,7 @@ __device__ __noinline__ void epilogue_setup(const KParams& P, SmallState& S, dou
 
 // Epilogue after pass kp: Algorithm 2's normalisation of R_kp (its norm is
 // s_{kp-1} = h_{kp,kp-1}), the window coefficients h_{i,kp} by modified
-// Gram-Schmidt (lines 7-10) reproduced from the inner products, the
+// Gram-Schmidt of Algorithm 2 reproduced from the inner products, the
 // coefficients of the next pass, and the end of an attempt.
 __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, double* lds) {
   Ctrl& C = S.C;
@@ -403,7 +409,7 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
       C.phase = kPhaseDone;
       action = 3;
     } else if (k > 1 && (s == 0.0 || s <= 1e-12 * S.unorm_prev)) {
-      h_set(S, P, k, k - 1, 0.0);               // happy breakdown (Alg. 2, lines 12-14)
+      h_set(S, P, k, k - 1, 0.0);               // happy breakdown (Alg. 2)
       C.breakdown = 1;
       C.s_last = s;
       action = (C.mode == kModeBasis) ? 3 : 2;
@@ -428,7 +434,7 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
         for (int c = 0; c < kPM; ++c) yd += yi[c] * ykr[c];
         gk[i - (k - kWinMax + 1)] = (red[kDotG + d] + yd) * S.sinv[i] * si;
       }
-      // modified Gram-Schmidt over the window [dlo, k] (Alg. 2, lines 7-10)
+      // modified Gram-Schmidt over the window [dlo, k] (Alg. 2)
       double hk[kWinMax];
       for (int i = dlo; i <= k; ++i) {
         double raw;
@@ -479,7 +485,7 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
   publish(P, S);
 }
 
-// Epilogue after the gather: advance T_now (Alg. 1, line 24) and start the next substep.
+// Epilogue after the gather: advance T_now (Alg. 1) and start the next substep.
 __device__ __noinline__ void epilogue_gather(const KParams& P, SmallState& S) {
   if (threadIdx.x == 0) {
     Ctrl& C = S.C;
