@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-substeps", type=int, default=2)
     ap.add_argument("--traffic-json", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run one plain device copy of MIB MiB (a known-size "
+                         "kernel that HBM traffic counters are scaled by)")
     return ap.parse_args()
 
 
@@ -180,6 +183,15 @@ def main():
         "matvecs_per_s": sum(st["matvecs"] for *_, st in records) / wall,
         "per_tau": per_tau,
     }
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)      # elementwise kernel: reads and writes nbytes
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nbytes
+        del src, dst
     if not args.no_cpu_baseline:
         sample = W.cfg2(side, taus[0], q=args.q)
         out["cpu_baseline"] = cpu_baseline(sample, taus, args.cpu_sample_substeps)

@@ -25,6 +25,8 @@
 
 namespace kiops {
 
+constexpr int kXcds = 8;   // accelerator complex dies of an MI355X
+
 template <typename T, int PB>
 struct Stencil2D {
   static constexpr int TX = 64, TY = 16;
@@ -88,7 +90,18 @@ struct Stencil2D {
     const bool ring = t < kRingPos;
     ring_pos(ring ? t : 0, prx[4], pry[4]);
 
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
+    // workgroup b runs on XCD b % 8.  Each XCD takes one contiguous band of the
+    // row-major tile sequence, and its workgroups sweep the band together, so
+    // the tiles in flight on an XCD are horizontal and vertical neighbours and
+    // their halos and rings are served by that XCD's L2.
+    // (Grids smaller than 8 use as many bands as workgroups.)
+    const int nband = (int)gridDim.x < kXcds ? (int)gridDim.x : kXcds;
+    const int band = (int)blockIdx.x % nband;
+    const int nloc = ((int)gridDim.x - band + nband - 1) / nband;   // workgroups of this band
+    const int t_lo = (int)((int64_t)ntiles * band / nband);
+    const int t_hi = (int)((int64_t)ntiles * (band + 1) / nband);
+    for (int tile = t_lo + (int)blockIdx.x / nband; tile < t_hi; tile += nloc) {
       const int x0 = (tile % tiles_x) * TX;
       const int y0 = (tile / tiles_x) * TY;
       // ---- issue every load of the tile
