@@ -85,8 +85,10 @@ typedef struct {
 } kiops_operator_desc;
 
 /* Bounds of the Krylov dimension (Algorithm 1 inputs m_min, m_max; defaults
- * 10 and 128, Section 3.6.2) and a cap on substeps (default 100000).  A zero
- * field takes its default.  m_max must not exceed KIOPS_M_MAX_LIMIT. */
+ * 10 and 128, Section 3.6.2; m_max defaults to 64 for KIOPS_MIXED operators,
+ * whose FP32 basis loses accuracy over longer recurrences) and a cap on
+ * substeps (default 100000).  A zero field takes its default.  m_max must not
+ * exceed KIOPS_M_MAX_LIMIT. */
 typedef struct {
   int32_t m_min;
   int32_t m_max;
@@ -115,10 +117,13 @@ typedef struct {
   double time_wait_s;     /* workgroup 0: time waiting for the other workgroups at barriers */
   double time_epilogue_s; /* serial epilogues: reductions, small exponential, controller */
   double time_expm_s;     /* part of time_epilogue_s spent in small exponentials */
-  /* With the environment variable KIOPS_PROFILE=1: sums over barriers of the
-   * latest and of the mean workgroup arrival after the previous release. */
+  /* With the environment variable KIOPS_PROFILE=1: sums over barriers (the
+   * first excepted) of the latest and of the mean workgroup arrival after the
+   * previous release, and of the latest and mean delay until a workgroup saw
+   * that release; barriers counts all barriers. */
   double arrive_max_s, arrive_mean_s;
   int64_t barriers;
+  double release_max_s, release_mean_s;
 } kiops_stats;
 
 typedef struct kiops_operator kiops_operator;

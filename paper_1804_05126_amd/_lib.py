@@ -64,6 +64,7 @@ class Stats(C.Structure):
         ("time_work_s", C.c_double), ("time_wait_s", C.c_double), ("time_epilogue_s", C.c_double),
         ("time_expm_s", C.c_double), ("arrive_max_s", C.c_double), ("arrive_mean_s", C.c_double),
         ("barriers", C.c_int64),
+        ("release_max_s", C.c_double), ("release_mean_s", C.c_double),
     ]
 
     def as_dict(self) -> dict:

@@ -12,6 +12,7 @@
 #include "../../include/kiops.h"
 #include "controller.h"
 #include "op_stencil2d.h"
+#include "op_stencil3d.h"
 #include "solver_kernel.h"
 
 using namespace kiops;
@@ -59,16 +60,55 @@ const void* stencil2d_kernel(int pb) {
   }
 }
 
+template <typename T>
+const void* stencil3d_kernel(int pb) {
+  switch (pb) {
+    case 0: return (const void*)kiops_solve_kernel<Stencil3D<T, 0>, T>;
+    case 2: return (const void*)kiops_solve_kernel<Stencil3D<T, 2>, T>;
+    case 4: return (const void*)kiops_solve_kernel<Stencil3D<T, 4>, T>;
+    default: return (const void*)kiops_solve_kernel<Stencil3D<T, 8>, T>;
+  }
+}
+
+// The 7-point marching pass serves 3-D operators and 2-D ones with a
+// diffusivity field (nz = 1); the 5-point tile pass serves constant-diffusivity 2-D.
+bool uses_3d(const kiops_operator* op) {
+  return op->d.kind == KIOPS_OP_STENCIL3D_7PT || (op->d.kind == KIOPS_OP_STENCIL2D_5PT && op->d.kappa);
+}
+
+// z planes per work item of the marching pass (nominal; sizes the grid)
+int zchunk(const kiops_operator* op) { return (int)std::min<int64_t>(16, op->d.nz); }
+
+// Number of z chunks for a grid of nwg workgroups: about nz / 16, raised (by at
+// most half) so that the item count is a multiple of the grid when that is
+// reachable, which gives every workgroup the same number of items.
+int zchunks(const kiops_operator* op, int nwg) {
+  using S = Stencil3D<double, 2>;
+  const int64_t txy = ((op->d.nx + S::TX - 1) / S::TX) * ((op->d.ny + S::TY - 1) / S::TY);
+  const int64_t nz = op->d.nz;
+  const int64_t base = (nz + zchunk(op) - 1) / zchunk(op);
+  for (int64_t c = base; c <= std::min<int64_t>(nz, base + base / 2); ++c)
+    if ((txy * c) % nwg == 0) return (int)c;
+  return (int)base;
+}
+
 // The kernel instantiation that serves an operator and p.
 const void* kernel_for(const kiops_operator* op, int p) {
-  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
-    if (op->d.precision == KIOPS_MIXED) return stencil2d_kernel<float>(p_bucket(p));
-    return stencil2d_kernel<double>(p_bucket(p));
-  }
+  const bool mixed = op->d.precision == KIOPS_MIXED;
+  if (uses_3d(op)) return mixed ? stencil3d_kernel<float>(p_bucket(p)) : stencil3d_kernel<double>(p_bucket(p));
+  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT)
+    return mixed ? stencil2d_kernel<float>(p_bucket(p)) : stencil2d_kernel<double>(p_bucket(p));
   return nullptr;
 }
 
 int64_t work_tiles(const kiops_operator* op) {
+  if (uses_3d(op)) {
+    using S = Stencil3D<double, 2>;
+    const int64_t tx = (op->d.nx + S::TX - 1) / S::TX;
+    const int64_t ty = (op->d.ny + S::TY - 1) / S::TY;
+    const int64_t zc = zchunk(op);
+    return tx * ty * ((op->d.nz + zc - 1) / zc);
+  }
   if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
     const int64_t tx = (op->d.nx + Stencil2D<double, 2>::TX - 1) / Stencil2D<double, 2>::TX;
     const int64_t ty = (op->d.ny + Stencil2D<double, 2>::TY - 1) / Stencil2D<double, 2>::TY;
@@ -84,6 +124,10 @@ kiops_status grid_size(const kiops_operator* op, int p, int* nwg) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess || per_cu < 1)
     return KIOPS_ERR_DEVICE;
+  // The 5-point tile pass runs best with two workgroups per CU (measured at
+  // 2048^2: 110 us per Krylov step against 120 us with three); the marching
+  // 7-point pass with all that fit.
+  if (!uses_3d(op)) per_cu = std::min(per_cu, 2);
   int64_t g = (int64_t)per_cu * op->cus;
   const char* ov = std::getenv("KIOPS_GRID");   // experiment override, capped by co-residency
   if (ov && std::atoi(ov) > 0) g = std::min<int64_t>(g, std::atoi(ov));
@@ -92,9 +136,14 @@ kiops_status grid_size(const kiops_operator* op, int p, int* nwg) {
   return KIOPS_OK;
 }
 
-void resolve_options(const kiops_options* o, int* m_min, int* m_max, int* max_sub) {
+// Default m_max: 128 (Section 3.6.2); 64 for the mixed form, whose FP32 basis
+// loses accuracy over long recurrences (measured on the 256^3 and 2048^2
+// workloads: relative error 2.6e-4 at m = 128 against 6.7e-6 at m <= 64).
+void resolve_options(const kiops_operator* op, const kiops_options* o, int* m_min, int* m_max,
+                     int* max_sub) {
+  const int m_default = op->d.precision == KIOPS_MIXED ? 64 : 128;
   *m_min = (o && o->m_min > 0) ? o->m_min : 10;
-  *m_max = (o && o->m_max > 0) ? o->m_max : 128;
+  *m_max = (o && o->m_max > 0) ? o->m_max : m_default;
   *max_sub = (o && o->max_substeps > 0) ? o->max_substeps : 100000;
 }
 
@@ -109,7 +158,7 @@ Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
   L.ctrl = take(sizeof(Ctrl));
   L.bar = take(sizeof(Barrier));
   L.arrive = take(sizeof(unsigned) * (size_t)nwg);
-  L.arrive_t = take(sizeof(uint64_t) * (size_t)nwg);
+  L.arrive_t = take(sizeof(uint64_t) * 3 * (size_t)nwg);
   L.H = take(sizeof(double) * kLdh * kLdh);
   L.G = take(sizeof(double) * kLdh * kLdh);
   L.Y = take(sizeof(double) * kLdh * kPM);
@@ -165,6 +214,48 @@ Stencil2D<T, PB> make_stencil2d(const kiops_operator* op, int p, const double* c
   return s;
 }
 
+template <typename T, int PB>
+Stencil3D<T, PB> make_stencil3d(const kiops_operator* op, int p, const double* const* V, char* ws,
+                                const Layout& L) {
+  const auto& d = op->d;
+  Stencil3D<T, PB> s{};
+  s.N = op->N;
+  s.nx = (int)d.nx;
+  s.ny = (int)d.ny;
+  s.nz = (int)d.nz;
+  s.tiles_x = (int)((d.nx + Stencil3D<T, PB>::TX - 1) / Stencil3D<T, PB>::TX);
+  s.tiles_y = (int)((d.ny + Stencil3D<T, PB>::TY - 1) / Stencil3D<T, PB>::TY);
+  s.nchunks = zchunks(op, L.nwg);
+  s.nitems = s.tiles_x * s.tiles_y * s.nchunks;
+  s.h2inv = (T)(1.0 / (d.h * d.h));
+  s.half_h2inv = (T)(0.5 / (d.h * d.h));
+  s.cx = (T)(d.adv[0] / (2.0 * d.h));
+  s.cy = (T)(d.adv[1] / (2.0 * d.h));
+  s.cz = (T)(d.adv[2] / (2.0 * d.h));
+  s.diff = (T)d.diff;
+  s.p = p;
+  const bool mixed = d.precision == KIOPS_MIXED;
+  for (int c = 0; c < kPM; ++c) s.B[c] = nullptr;
+  if (mixed) {
+    T* bc = reinterpret_cast<T*>(ws + L.bcopy);
+    for (int c = 0; c < p; ++c) s.B[c] = bc + (size_t)c * op->N;
+    T* coef = reinterpret_cast<T*>(ws + L.coef);
+    s.r_src = d.reaction;
+    s.r_dst = d.reaction ? coef : nullptr;
+    s.r = s.r_dst;
+    s.k_src = d.kappa;
+    s.k_dst = d.kappa ? coef + (d.reaction ? (size_t)op->N : 0) : nullptr;
+    s.kappa = s.k_dst;
+  } else {
+    for (int c = 0; c < p; ++c) s.B[c] = reinterpret_cast<const T*>(V[p - c]);
+    s.r = reinterpret_cast<const T*>(d.reaction);
+    s.kappa = reinterpret_cast<const T*>(d.kappa);
+    s.r_src = s.k_src = nullptr;
+    s.r_dst = s.k_dst = nullptr;
+  }
+  return s;
+}
+
 KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double tau, int p,
                     const double* const* V, double tol, int m_init, int q, int m_min, int m_max,
                     int max_sub, int mode, double* w) {
@@ -216,7 +307,8 @@ void stage_op(unsigned char* host_block, const OpT& o) {
 kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, const double* const* V,
                        Ctrl* host_ctrl, unsigned* host_abort) {
   char* ws = reinterpret_cast<char*>(op->ws);
-  hipLaunchKernelGGL(kiops_reset_kernel, dim3(1), dim3(256), 0, op->stream, P.bar, P.ctrl, P.arrive, L.nwg);
+  hipLaunchKernelGGL(kiops_reset_kernel, dim3(1), dim3(256), 0, op->stream, P.bar, P.ctrl, P.arrive, L.nwg,
+                     P.arrive_t);
   if (!hip_ok(hipGetLastError())) return KIOPS_ERR_DEVICE;
   hipError_t e = hipSuccess;
   // parameter block: KParams at +0, operator struct at +2048 (host staging buffer)
@@ -228,7 +320,19 @@ kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, c
   void* dOp = ws + L.params + 2048;
   const void* fn = kernel_for(op, p);
   if (!fn) return KIOPS_ERR_UNSUPPORTED;
-  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
+  if (uses_3d(op)) {
+    const bool mixed = op->d.precision == KIOPS_MIXED;
+    switch (p_bucket(p)) {
+      case 0: mixed ? stage_op(host_block, make_stencil3d<float, 0>(op, p, V, ws, L))
+                    : stage_op(host_block, make_stencil3d<double, 0>(op, p, V, ws, L)); break;
+      case 2: mixed ? stage_op(host_block, make_stencil3d<float, 2>(op, p, V, ws, L))
+                    : stage_op(host_block, make_stencil3d<double, 2>(op, p, V, ws, L)); break;
+      case 4: mixed ? stage_op(host_block, make_stencil3d<float, 4>(op, p, V, ws, L))
+                    : stage_op(host_block, make_stencil3d<double, 4>(op, p, V, ws, L)); break;
+      default: mixed ? stage_op(host_block, make_stencil3d<float, 8>(op, p, V, ws, L))
+                     : stage_op(host_block, make_stencil3d<double, 8>(op, p, V, ws, L)); break;
+    }
+  } else if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
     const bool mixed = op->d.precision == KIOPS_MIXED;
     switch (p_bucket(p)) {
       case 0: mixed ? stage_op(host_block, make_stencil2d<float, 0>(op, p, V, ws, L))
@@ -268,6 +372,8 @@ void fill_stats(const Ctrl& c, int nwg, double clock_hz, kiops_stats* st) {
   st->time_expm_s = (double)c.t_expm / clock_hz;
   st->arrive_max_s = (double)c.t_arrive_max / clock_hz;
   st->arrive_mean_s = (double)c.t_arrive_mean / clock_hz;
+  st->release_max_s = (double)c.t_release_max / clock_hz;
+  st->release_mean_s = (double)c.t_release_mean / clock_hz;
   st->barriers = (int64_t)c.n_barriers;
   st->m_last = c.m;
   st->substeps = c.substeps;
@@ -370,6 +476,8 @@ kiops_status kiops_create_operator(const kiops_operator_desc* desc, void* hip_st
     if (d.kind == KIOPS_OP_STENCIL2D_5PT && d.nz != 1) return KIOPS_ERR_INVALID_ARG;
     if (d.nx > (1 << 30) || d.ny > (1 << 30) || d.nz > (1 << 30)) return KIOPS_ERR_INVALID_ARG;
     N = d.nx * d.ny * d.nz;
+    // the passes address every array with 32-bit byte offsets
+    if (N * (int64_t)sizeof(double) >= ((int64_t)1 << 32)) return KIOPS_ERR_INVALID_ARG;
     if (!std::isfinite(d.diff) || !std::isfinite(d.adv[0]) || !std::isfinite(d.adv[1]) ||
         !std::isfinite(d.adv[2]))
       return KIOPS_ERR_INVALID_ARG;
@@ -422,7 +530,7 @@ kiops_status kiops_workspace_bytes(const kiops_operator* op, int p, int q, const
                                    size_t* bytes) {
   if (!op || !bytes || p < 0 || p > KIOPS_P_MAX || q < 0 || q > 8) return KIOPS_ERR_INVALID_ARG;
   int m_min, m_max, max_sub;
-  resolve_options(opts, &m_min, &m_max, &max_sub);
+  resolve_options(op, opts, &m_min, &m_max, &max_sub);
   if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max) return KIOPS_ERR_INVALID_ARG;
   int nwg = 0;
   kiops_status s = grid_size(op, p, &nwg);
@@ -449,10 +557,10 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
   kiops_status s = check_vectors(op, p, V, w);
   if (s != KIOPS_OK) return s;
   int m_min, m_max, max_sub;
-  resolve_options(opts, &m_min, &m_max, &max_sub);
+  resolve_options(op, opts, &m_min, &m_max, &max_sub);
   if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max || m_min < 1) return KIOPS_ERR_INVALID_ARG;
   if (q == 0 || q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
-  if (op->d.kind != KIOPS_OP_STENCIL2D_5PT || op->d.kappa) return KIOPS_ERR_UNSUPPORTED;
+  if (!kernel_for(op, p)) return KIOPS_ERR_UNSUPPORTED;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (tau == 0.0) {
     if (w != V[0] &&
@@ -484,7 +592,7 @@ kiops_status kiops_iop_basis(kiops_operator* op, int p, const double* const* V, 
   if (!V || p < 0 || p > KIOPS_P_MAX) return KIOPS_ERR_INVALID_ARG;
   for (int k = 0; k <= p; ++k)
     if (!V[k]) return KIOPS_ERR_INVALID_ARG;
-  if (op->d.kind != KIOPS_OP_STENCIL2D_5PT || op->d.kappa) return KIOPS_ERR_UNSUPPORTED;
+  if (!kernel_for(op, p)) return KIOPS_ERR_UNSUPPORTED;
   int nwg = 0;
   kiops_status s = grid_size(op, p, &nwg);
   if (s != KIOPS_OK) return s;

@@ -25,8 +25,6 @@
 
 namespace kiops {
 
-constexpr int kXcds = 8;   // accelerator complex dies of an MI355X
-
 template <typename T, int PB>
 struct Stencil2D {
   static constexpr int TX = 64, TY = 16;
@@ -37,6 +35,7 @@ struct Stencil2D {
   static constexpr int kRegionLoads = (kRegion + kThreads - 1) / kThreads;
   static constexpr int kPos = 5;                   // 4 tile positions + 1 ring position
   static constexpr int kLdsT = RX * RY + SX * SY;  // elements of T
+  static constexpr int kLdsDoubles = (int)((kLdsT * sizeof(T) + 7) / 8);
   // occupancy target: the register footprint of a tile's loads grows with PB
   static constexpr int kWavesPerEU = (PB >= 4 && sizeof(T) == 8) ? 3 : 4;
 
@@ -94,8 +93,8 @@ struct Stencil2D {
     // workgroup b runs on XCD b % 8.  Each XCD takes one contiguous band of the
     // row-major tile sequence, and its workgroups sweep the band together, so
     // the tiles in flight on an XCD are horizontal and vertical neighbours and
-    // their halos and rings are served by that XCD's L2.
-    // (Grids smaller than 8 use as many bands as workgroups.)
+    // their halos and rings are served by that XCD's L2.  (Grids smaller than
+    // 8 use as many bands as workgroups.)
     const int nband = (int)gridDim.x < kXcds ? (int)gridDim.x : kXcds;
     const int band = (int)blockIdx.x % nband;
     const int nloc = ((int)gridDim.x - band + nband - 1) / nband;   // workgroups of this band

@@ -22,6 +22,7 @@ constexpr int kPM = KIOPS_P_MAX;
 constexpr int kWinMax = 4;                          // windows q <= 4 use register accumulators
 constexpr int kTraceMax = 4096;
 constexpr int kTraceStride = 6;
+constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
 
 enum Phase : int32_t { kPhasePass = 0, kPhaseGather = 1, kPhaseDone = 2 };
 enum Mode : int32_t { kModeSolve = 0, kModeBasis = 1 };
@@ -58,13 +59,16 @@ struct Ctrl {
   uint64_t t_work, t_wait, t_epi, t_last;
   // optional profile: small exponentials, latest / mean arrival after a release
   uint64_t t_expm, t_arrive_max, t_arrive_mean, n_barriers;
+  uint64_t t_release_max, t_release_mean;   // delay until a workgroup sees the release
 };
 
+// Release word and abort flag on separate 128-byte lines: every workgroup
+// polls `gen`, and the abort flag is read far less often.
 struct Barrier {
-  unsigned count;
   unsigned gen;
+  unsigned pad0[31];
   unsigned abort;
-  unsigned pad;
+  unsigned pad1[31];
 };
 
 // Kernel parameters common to all operators (passed by value).
@@ -84,7 +88,8 @@ struct KParams {
   Ctrl* ctrl;
   Barrier* bar;
   unsigned* arrive;            // per-workgroup arrival epochs (grid barrier)
-  uint64_t* arrive_t;          // per-workgroup arrival clocks (profile only)
+  uint64_t* arrive_t;          // profile only: per-workgroup arrival clocks, release-seen clocks,
+                               // and per-workgroup sums of arrival after release
   double* H;                   // kLdh x kLdh
   double* G;                   // Gram matrix of the normalised basis, kLdh x kLdh
   double* Y;                   // trailing (y) parts of R_i, kLdh x kPM

@@ -81,53 +81,76 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
       __threadfence();
       __hip_atomic_store(&P.arrive[blockIdx.x], epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
       const uint64_t t0 = (uint64_t)wall_clock64();
-      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT) != epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if (spin_expired(b, t0, P.spin_limit)) break;
+      for (unsigned spins = 1;; ++spins) {
+        if (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) break;
+        __builtin_amdgcn_s_sleep(2);
+        if ((spins & 63u) == 0 && spin_expired(b, t0, P.spin_limit)) break;
       }
+      if (P.profile) P.arrive_t[P.nwg + blockIdx.x] = (uint64_t)wall_clock64();
       __threadfence();
     }
     __syncthreads();
     return;
   }
   const uint64_t t0 = (uint64_t)wall_clock64();
-  for (;;) {
+  for (unsigned spins = 1;; ++spins) {
     int ok = 1;
     for (unsigned w = 1 + threadIdx.x; w < (unsigned)P.nwg; w += kThreads)
       ok &= (__hip_atomic_load(&P.arrive[w], __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) ? 1 : 0;
     if (__syncthreads_and(ok)) break;
-    if (threadIdx.x == 0) {                      // the give-up decision is thread 0's
-      __builtin_amdgcn_s_sleep(1);
-      S.expired = spin_expired(b, t0, P.spin_limit) ? 1 : 0;
+    if ((spins & 15u) == 0) {
+      if (threadIdx.x == 0) S.expired = spin_expired(b, t0, P.spin_limit) ? 1 : 0;   // thread 0 decides
+      __syncthreads();
+      if (S.expired) break;
     }
-    __syncthreads();
-    if (S.expired) break;
   }
   __threadfence();
   __syncthreads();
   const uint64_t t1 = (uint64_t)wall_clock64();
   if (P.profile) {
-    // arrival spread: latest and mean arrival after the previous release
-    uint64_t mx = 0, sum = 0;
+    // arrival spread and release delay: latest and mean, after the previous release
+    uint64_t mx = 0, sum = 0, rmx = 0, rsum = 0;
     for (int w = 1 + threadIdx.x; w < P.nwg; w += kThreads) {
       const uint64_t a = P.arrive_t[w] - S.C.t_last;
+      const uint64_t r = P.arrive_t[P.nwg + w] - S.C.t_last;
+      if (S.C.n_barriers > 0) P.arrive_t[2 * P.nwg + w] += a;   // per-workgroup sum
       mx = a > mx ? a : mx;
       sum += a;
+      rmx = r > rmx ? r : rmx;
+      rsum += r;
     }
     for (int off = 32; off > 0; off >>= 1) {
       const uint64_t om = __shfl_down(mx, off, 64);
       const uint64_t os = __shfl_down(sum, off, 64);
+      const uint64_t rm = __shfl_down(rmx, off, 64);
+      const uint64_t rs = __shfl_down(rsum, off, 64);
       mx = om > mx ? om : mx;
       sum += os;
+      rmx = rm > rmx ? rm : rmx;
+      rsum += rs;
     }
-    __shared__ uint64_t s_mx[kThreads / 64], s_sum[kThreads / 64];
-    if ((threadIdx.x & 63) == 0) { s_mx[threadIdx.x >> 6] = mx; s_sum[threadIdx.x >> 6] = sum; }
+    __shared__ uint64_t s_mx[kThreads / 64], s_sum[kThreads / 64], s_rmx[kThreads / 64], s_rsum[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) {
+      s_mx[threadIdx.x >> 6] = mx;
+      s_sum[threadIdx.x >> 6] = sum;
+      s_rmx[threadIdx.x >> 6] = rmx;
+      s_rsum[threadIdx.x >> 6] = rsum;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-      for (int q = 1; q < kThreads / 64; ++q) { mx = s_mx[q] > mx ? s_mx[q] : mx; sum += s_sum[q]; }
-      mx = s_mx[0] > mx ? s_mx[0] : mx;
-      S.C.t_arrive_max += mx;
-      S.C.t_arrive_mean += P.nwg > 1 ? sum / (uint64_t)(P.nwg - 1) : 0;
+      for (int q = 1; q < kThreads / 64; ++q) {
+        mx = s_mx[q] > mx ? s_mx[q] : mx;
+        sum += s_sum[q];
+        rmx = s_rmx[q] > rmx ? s_rmx[q] : rmx;
+        rsum += s_rsum[q];
+      }
+      const uint64_t others = P.nwg > 1 ? (uint64_t)(P.nwg - 1) : 1;
+      if (S.C.n_barriers > 0) {   // the first barrier has no previous release
+        S.C.t_arrive_max += mx;
+        S.C.t_arrive_mean += sum / others;
+        S.C.t_release_max += rmx;
+        S.C.t_release_mean += rsum / others;
+      }
       S.C.n_barriers += 1;
     }
     __syncthreads();
@@ -148,6 +171,8 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
     P.ctrl->t_expm = C.t_expm;
     P.ctrl->t_arrive_max = C.t_arrive_max;
     P.ctrl->t_arrive_mean = C.t_arrive_mean;
+    P.ctrl->t_release_max = C.t_release_max;
+    P.ctrl->t_release_mean = C.t_release_mean;
     P.ctrl->n_barriers = C.n_barriers;
     __threadfence();
     __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
@@ -160,15 +185,15 @@ __device__ inline bool aborted(const KParams& P) {
 }
 
 // out[d] = sum over workgroups of partials[wg][d], d < kDotSlots, in a fixed
-// order (workgroup index, then lanes, then waves).  All loads are issued
-// before the first add.
-__device__ inline void reduce_partials(const KParams& P, double* out, double* lds) {
+// order (workgroup index, then lanes, then waves).  Loads are issued four rows
+// per thread at a time.
+__device__ inline void reduce_partials(const KParams& P, double* out, double* lds, int rows) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   double acc[kDotSlots];
 #pragma unroll
   for (int d = 0; d < kDotSlots; ++d) acc[d] = 0.0;
   int w = t;
-  for (; w + 3 * kThreads < P.nwg; w += 4 * kThreads) {
+  for (; w + 3 * kThreads < rows; w += 4 * kThreads) {
     double v[4][kDotSlots];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -179,7 +204,7 @@ __device__ inline void reduce_partials(const KParams& P, double* out, double* ld
 #pragma unroll
       for (int d = 0; d < kDotSlots; ++d) acc[d] += v[u][d];
   }
-  for (; w < P.nwg; w += kThreads)
+  for (; w < rows; w += kThreads)
 #pragma unroll
     for (int d = 0; d < kDotSlots; ++d) acc[d] += P.partials[(int64_t)w * P.ndot_stride + d];
 #pragma unroll
@@ -328,7 +353,7 @@ __device__ __noinline__ void attempt_end(const KParams& P, SmallState& S, int j,
 
 // Epilogue after the setup phase.
 __device__ __noinline__ void epilogue_setup(const KParams& P, SmallState& S, double* lds) {
-  reduce_partials(P, S.red, lds);
+  reduce_partials(P, S.red, lds, P.nwg);
   for (int e = threadIdx.x; e < kLdh * (kWinMax + 1); e += kThreads) (&S.Hb[0][0])[e] = 0.0;
   for (int e = threadIdx.x; e < kRingRows * kWinMax; e += kThreads) (&S.Gw[0][0])[e] = 0.0;
   for (int e = threadIdx.x; e < kLdh; e += kThreads) S.sinv[e] = 0.0;
@@ -377,7 +402,7 @@ __device__ __noinline__ void epilogue_setup(const KParams& P, SmallState& S, dou
 // coefficients of the next pass, and the end of an attempt.
 __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, double* lds) {
   Ctrl& C = S.C;
-  reduce_partials(P, S.red, lds);
+  reduce_partials(P, S.red, lds, P.nwg);
   if (threadIdx.x == 0) {
     int action = 0;
     const int k = C.kp;
@@ -605,7 +630,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(O
 kiops_solve_kernel(const KParams* __restrict__ Pp, const Op* __restrict__ opp) {
   const KParams& P = *Pp;
   const Op& op = *opp;
-  __shared__ double lds[kLdsDoubles];
+  // pass tiles (size set by the operator) / small-exponential and reduction staging
+  constexpr int kLds = Op::kLdsDoubles > kLdsDoubles ? Op::kLdsDoubles : kLdsDoubles;
+  __shared__ double lds[kLds];
   __shared__ PassCtx<T> pctx;
   __shared__ SmallState S;       // used by workgroup 0 only
   __shared__ int s_phase;
@@ -617,6 +644,7 @@ kiops_solve_kernel(const KParams* __restrict__ Pp, const Op* __restrict__ opp) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     S.C.t_work = S.C.t_wait = S.C.t_epi = 0;
     S.C.t_expm = S.C.t_arrive_max = S.C.t_arrive_mean = S.C.n_barriers = 0;
+    S.C.t_release_max = S.C.t_release_mean = 0;
     S.C.t_last = (uint64_t)wall_clock64();
   }
 
@@ -646,17 +674,17 @@ kiops_solve_kernel(const KParams* __restrict__ Pp, const Op* __restrict__ opp) {
   }
 }
 
-__global__ void kiops_reset_kernel(Barrier* b, Ctrl* c, unsigned* arrive, int nwg) {
+__global__ void kiops_reset_kernel(Barrier* b, Ctrl* c, unsigned* arrive, int nwg, uint64_t* arrive_t) {
   for (int i = threadIdx.x; i < nwg; i += blockDim.x) arrive[i] = 0u;
+  for (int i = threadIdx.x; i < 3 * nwg; i += blockDim.x) arrive_t[i] = 0u;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    b->count = 0;
     b->gen = 0;
     b->abort = 0;
-    b->pad = 0;
     c->phase = kPhaseDone;
     c->status = KIOPS_OK;
     c->t_work = c->t_wait = c->t_epi = 0;
     c->t_expm = c->t_arrive_max = c->t_arrive_mean = c->n_barriers = 0;
+    c->t_release_max = c->t_release_mean = 0;
   }
 }
 
