@@ -11,8 +11,11 @@ e^M = (e^{M / 2^s})^{2^s} it gives a plainly correct algorithm:
   3. square the result s times.
 
 This is the scaling-and-squaring idea the paper uses for its small exponential
-(Section 3.3.1) but with a truncated Taylor series in place of the diagonal
-Pade approximant, so it shares no formula with the device code.
+(Section 3.3.1) with the series itself in place of the diagonal Pade
+approximant.  It is written independently of the device routine (which
+evaluates a fixed-degree Taylor polynomial by Paterson-Stockmeyer with its own
+scaling thresholds) and is pinned against closed forms and SciPy's Pade-based
+expm in the tests.
 """
 
 from __future__ import annotations
