@@ -34,8 +34,9 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t params, ctrl, bar, arrive, arrive_t, H, G, Y, sinv, unorm, partials, expm, trace, slots, bcopy, coef, total;
-  int nwg, ndot_stride;
+  size_t params, ctrl, bar, arrive, arrive_t, H, G, Y, sinv, coefc, fullc, partials, dpart, expm, trace, slots,
+      ubuf, bcopy, coef, total;
+  int nwg, ndot_stride, q;
 };
 
 int elem_size(const kiops_operator* op) { return op->d.precision == KIOPS_MIXED ? 4 : 8; }
@@ -152,8 +153,8 @@ Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
   L.nwg = nwg;
+  L.q = q;
   L.ndot_stride = std::max(kPM, kDotSlots);
-  (void)q;
   L.params = take(4096);   // KParams followed by the operator struct
   L.ctrl = take(sizeof(Ctrl));
   L.bar = take(sizeof(Barrier));
@@ -163,12 +164,15 @@ Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
   L.G = take(sizeof(double) * kLdh * kLdh);
   L.Y = take(sizeof(double) * kLdh * kPM);
   L.sinv = take(sizeof(double) * kLdh);
-  L.unorm = take(sizeof(double) * kLdh);
+  L.coefc = take(sizeof(double) * kLdh);
+  L.fullc = take(sizeof(double) * 2 * kLdh);
   L.partials = take(sizeof(double) * (size_t)nwg * L.ndot_stride);
+  L.dpart = take(q == 0 ? sizeof(double) * (size_t)nwg * kDotFullStride : 0);
   L.expm = take(sizeof(double) * (size_t)kExpmSlots * kExpmSlot);
   L.trace = take(sizeof(double) * (size_t)kTraceMax * kTraceStride);
   const size_t es = (size_t)elem_size(op);
   L.slots = take(es * (size_t)(m_max + 1) * (size_t)op->N);
+  L.ubuf = take(q == 0 ? es * (size_t)op->N : 0);
   L.bcopy = take(op->d.precision == KIOPS_MIXED ? es * (size_t)p * op->N : 0);
   L.coef = take(op->d.precision == KIOPS_MIXED ? es * (size_t)coef_streams(op) * op->N : 0);
   L.total = off;
@@ -197,6 +201,7 @@ Stencil2D<T, PB> make_stencil2d(const kiops_operator* op, int p, const double* c
   s.wS = (T)(cD + cy);
   s.wC = (T)(-4.0 * cD);
   s.p = p;
+  s.ubuf = L.q == 0 ? reinterpret_cast<T*>(ws + L.ubuf) : nullptr;
   const bool mixed = d.precision == KIOPS_MIXED;
   for (int c = 0; c < kPM; ++c) s.B[c] = nullptr;
   if (mixed) {
@@ -234,6 +239,7 @@ Stencil3D<T, PB> make_stencil3d(const kiops_operator* op, int p, const double* c
   s.cz = (T)(d.adv[2] / (2.0 * d.h));
   s.diff = (T)d.diff;
   s.p = p;
+  s.ubuf = L.q == 0 ? reinterpret_cast<T*>(ws + L.ubuf) : nullptr;
   const bool mixed = d.precision == KIOPS_MIXED;
   for (int c = 0; c < kPM; ++c) s.B[c] = nullptr;
   if (mixed) {
@@ -290,7 +296,10 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   P.G = reinterpret_cast<double*>(ws + L.G);
   P.Y = reinterpret_cast<double*>(ws + L.Y);
   P.sinv = reinterpret_cast<double*>(ws + L.sinv);
-  P.unorm = reinterpret_cast<double*>(ws + L.unorm);
+  P.coefc = reinterpret_cast<double*>(ws + L.coefc);
+  P.fullc = reinterpret_cast<double*>(ws + L.fullc);
+  P.dpart = reinterpret_cast<double*>(ws + L.dpart);
+  P.ubuf = q == 0 ? ws + L.ubuf : nullptr;
   P.partials = reinterpret_cast<double*>(ws + L.partials);
   P.expm = reinterpret_cast<double*>(ws + L.expm);
   P.trace = reinterpret_cast<double*>(ws + L.trace);
@@ -559,7 +568,7 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
   int m_min, m_max, max_sub;
   resolve_options(op, opts, &m_min, &m_max, &max_sub);
   if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max || m_min < 1) return KIOPS_ERR_INVALID_ARG;
-  if (q == 0 || q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
+  if (q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
   if (!kernel_for(op, p)) return KIOPS_ERR_UNSUPPORTED;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (tau == 0.0) {
@@ -587,7 +596,7 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
 
 kiops_status kiops_iop_basis(kiops_operator* op, int p, const double* const* V, int m, int q,
                              double* basis, double* H, int* j_done, double* beta, double* nu_out) {
-  if (!op || !basis || !H || m < 1 || m > KIOPS_M_MAX_LIMIT || q < 1 || q > kWinMax)
+  if (!op || !basis || !H || m < 1 || m > KIOPS_M_MAX_LIMIT || q < 0 || q > kWinMax)
     return KIOPS_ERR_INVALID_ARG;
   if (!V || p < 0 || p > KIOPS_P_MAX) return KIOPS_ERR_INVALID_ARG;
   for (int k = 0; k <= p; ++k)

@@ -47,6 +47,7 @@ struct Stencil2D {
   int p;
   const double* r_src;   // mixed precision: float copy r <- r_src made at setup
   T* r_dst;
+  T* ubuf;               // full window: U_kp output
 
   __device__ void setup_coefficients(const KParams& P, int64_t gt, int64_t gs) const {
     if (r_dst && r_src)
@@ -80,6 +81,7 @@ struct Stencil2D {
     const __amdgpu_buffer_rsrc_t rsW = make_rsrc(first ? w : nullptr, (uint64_t)N * 8);
     const __amdgpu_buffer_rsrc_t rsr = make_rsrc(r, nb);
     const __amdgpu_buffer_rsrc_t rsOut = make_rsrc(c.write_out ? Rout : nullptr, nb);
+    const __amdgpu_buffer_rsrc_t rsU = make_rsrc(c.store_u ? ubuf : nullptr, nb);
     __amdgpu_buffer_rsrc_t rsB[PB > 0 ? PB : 1];
 #pragma unroll
     for (int k = 0; k < PB; ++k) rsB[k] = make_rsrc(k < c.p ? B[k] : nullptr, nb);
@@ -164,9 +166,19 @@ struct Stencil2D {
             X = c.a * U;
             X = fma(c.bw[c.src], ctr, X);
             if (has_old) X = fma(c.bw[c.src - 1], ov[q], X);
-            if (more_old)
-              for (int i = c.flo; i < c.src - 1; ++i)
-                X = fma(c.bw[i], buf_ld(make_rsrc(bp.get(i), nb), goff[q], T(0)), X);
+            if (more_old) {
+              // older window vectors (a full window streams every earlier
+              // vector: eight loads in flight at a time)
+              int i = c.flo;
+              for (; i + 8 <= c.src - 1; i += 8) {
+                T v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = buf_ld(make_rsrc(bp.get(i + u), nb), goff[q], T(0));
+#pragma unroll
+                for (int u = 0; u < 8; ++u) X = fma(c.bw[i + u], v[u], X);
+              }
+              for (; i < c.src - 1; ++i) X = fma(c.bw[i], buf_ld(make_rsrc(bp.get(i), nb), goff[q], T(0)), X);
+            }
           }
           sX[(pry[q] + 1) * SX + (prx[q] + 1)] = X;
         }
@@ -186,6 +198,7 @@ struct Stencil2D {
         U = fma(wC + rv[i], X, U);
         U += bcur[i];
         buf_st(rsOut, valid ? goff[i] : kNoOffset, X);
+        buf_st(rsU, valid ? goff[i] : kNoOffset, U);
         const double Xd = valid ? (double)X : 0.0, Ud = valid ? (double)U : 0.0;
         acc.RR = fma(Xd, Xd, acc.RR);
         acc.UU = fma(Ud, Ud, acc.UU);

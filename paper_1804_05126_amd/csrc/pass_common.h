@@ -21,6 +21,7 @@ namespace kiops {
 template <typename T>
 struct PassCtx {
   int kp, src, flo, dlo, ngd, first, write_out, p;
+  int store_u;   // full window: also write U_kp (the inner products come from a later phase)
   T a;
   T bw[kLdh];
   T ybp[kPM];

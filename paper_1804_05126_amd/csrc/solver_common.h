@@ -24,7 +24,8 @@ constexpr int kTraceMax = 4096;
 constexpr int kTraceStride = 6;
 constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
 
-enum Phase : int32_t { kPhasePass = 0, kPhaseGather = 1, kPhaseDone = 2 };
+enum Phase : int32_t { kPhasePass = 0, kPhaseGather = 1, kPhaseDone = 2, kPhaseDots = 3 };
+constexpr int kDotFullStride = 2 * kLdh;            // full-window inner products per workgroup
 enum Mode : int32_t { kModeSolve = 0, kModeBasis = 1 };
 
 // Small solver state, in the workspace.  Written only inside epilogues.
@@ -94,7 +95,10 @@ struct KParams {
   double* G;                   // Gram matrix of the normalised basis, kLdh x kLdh
   double* Y;                   // trailing (y) parts of R_i, kLdh x kPM
   double* sinv;                // v_i = R_i * sinv[i]
-  double* unorm;               // ||A~ v_i||
+  double* coefc;               // full window: c_i = <v_i, A~ v_k>
+  double* fullc;               // full window: reduced <R_i, R_k>, <R_i, U_k> (interleaved)
+  double* dpart;               // full window: nwg x kDotFullStride partial inner products
+  void* ubuf;                  // full window: U_k = A~ R_k of the latest pass (elements of T)
   double* partials;            // nwg x ndot_stride
   double* expm;                // small-exponential scratch
   double* trace;               // kTraceMax x kTraceStride

@@ -36,6 +36,7 @@ struct SmallState {
   double Yw[kRingRows][kPM];         // y-part of R_i at row i % kRingRows
   double Gw[kRingRows][kWinMax];     // Gw[k % kRingRows][d] = G(k, k - kWinMax + 1 + d)
   double unorm_prev;                 // ||A~ v_{kp-1}||
+  double fy[kPM], fky[kPM], fsi, fck;  // full-window step: y_k, K y_k, 1/s_k, <R_k, U_k>
   double red[16];                    // reduced inner products
   int action, jj, again, expired;
 };
@@ -45,8 +46,13 @@ __device__ inline double h_get(const SmallState& S, int i, int k) {
   return (d >= 0 && d <= kWinMax) ? S.Hb[k][d] : 0.0;
 }
 __device__ inline void h_set(SmallState& S, const KParams& P, int i, int k, double v) {
-  S.Hb[k][i - (k - kWinMax + 1)] = v;
-  P.H[i * kLdh + k] = v;                      // device-memory copy (diagnostics export)
+  const int d = i - (k - kWinMax + 1);
+  if (d >= 0 && d <= kWinMax) S.Hb[k][d] = v;   // the band kept in LDS
+  P.H[i * kLdh + k] = v;                        // full copy in device memory
+}
+// H(i, k): the LDS band for windowed runs, device memory for a full window
+__device__ inline double h_any(const SmallState& S, const KParams& P, int i, int k) {
+  return S.C.q == 0 ? P.H[i * kLdh + k] : h_get(S, i, k);
 }
 __device__ inline double g_get(const SmallState& S, int i, int l) {   // |i - l| < kWinMax
   if (i < l) { const int t = i; i = l; l = t; }
@@ -284,7 +290,7 @@ __device__ __noinline__ void attempt_end(const KParams& P, SmallState& S, int j,
       double cs = 0.0;
       for (int r = 0; r < n16; ++r) {
         double v = 0.0;
-        if (r < j && c < j) v = tau * h_get(S, r + 1, c + 1);
+        if (r < j && c < j) v = tau * h_any(S, P, r + 1, c + 1);
         else if (c == j && r == 0) v = tau;
         A[r * kExpmLd + c] = v;
         cs += fabs(v);
@@ -396,57 +402,98 @@ __device__ __noinline__ void epilogue_setup(const KParams& P, SmallState& S, dou
   publish(P, S);
 }
 
-// Epilogue after pass kp: Algorithm 2's normalisation of R_kp (its norm is
-// s_{kp-1} = h_{kp,kp-1}), the window coefficients h_{i,kp} by modified
-// Gram-Schmidt of Algorithm 2 reproduced from the inner products, the
-// coefficients of the next pass, and the end of an attempt.
+// Normalisation of R_k after pass k (thread 0): its norm over N + p entries is
+// s_{k-1} = h_{k,k-1}.  Returns -1 to continue with the orthogonalisation,
+// else the action: 2 breakdown (end the attempt), 3 done.
+__device__ inline int step_normalise(const KParams& P, SmallState& S, int k, double* ykr, double* Ky,
+                                     double& Ck_out, double& si_out) {
+  Ctrl& C = S.C;
+  const int p = C.p;
+  const double* red = S.red;
+  const double* yk = C.q == 0 ? P.Y + k * kPM : y_row(S, k);
+#pragma unroll
+  for (int c = 0; c < kPM; ++c) ykr[c] = yk[c];
+#pragma unroll
+  for (int c = 0; c < kPM; ++c) Ky[c] = (c + 1 < kPM && c + 1 < p) ? ykr[c + 1] : 0.0;   // K y
+  double RR = red[kDotRR], UU = red[kDotUU], Ck = red[kDotCk];
+#pragma unroll
+  for (int c = 0; c < kPM; ++c) { RR += ykr[c] * ykr[c]; UU += Ky[c] * Ky[c]; Ck += ykr[c] * Ky[c]; }
+  C.matvecs += 1;
+  C.alg_bytes += pass_bytes(P, k, C.flo);
+  bool finite = isfinite(RR) && isfinite(UU) && isfinite(Ck);
+  for (int d = 0; d < k - C.dlo; ++d) finite = finite && isfinite(red[kDotG + d]) && isfinite(red[kDotC + d]);
+  const double s = sqrt(RR);
+  if (!finite) {
+    C.status = KIOPS_ERR_NONFINITE;
+    C.phase = kPhaseDone;
+    return 3;
+  }
+  if (k == 1 && s == 0.0) {
+    C.beta = 0.0;                             // zero start vector: w stays zero
+    C.T_now = C.T_end;
+    C.phase = kPhaseDone;
+    return 3;
+  }
+  if (k > 1 && (s == 0.0 || s <= 1e-12 * S.unorm_prev)) {
+    h_set(S, P, k, k - 1, 0.0);               // happy breakdown (Alg. 2)
+    C.breakdown = 1;
+    C.s_last = s;
+    const int action = (C.mode == kModeBasis) ? 3 : 2;
+    if (action == 3) C.phase = kPhaseDone;
+    return action;
+  }
+  if (k == 1) C.beta = s;
+  else h_set(S, P, k, k - 1, s);
+  C.s_last = s;
+  const double si = 1.0 / s;
+  S.sinv[k] = si;
+  P.sinv[k] = si;
+  S.unorm_prev = sqrt(UU) * si;
+  Ck_out = Ck;
+  si_out = si;
+  return -1;
+}
+
+// Next pass and the attempt bookkeeping once column k of H is known (thread 0).
+__device__ inline int step_advance(SmallState& S, int k, int flo_next) {
+  Ctrl& C = S.C;
+  int action = 0;
+  C.flo = flo_next;
+  C.kp = k + 1;
+  C.dlo = (C.q == 0) ? k + 1 : ((k + 1 - C.q + 1) > 1 ? (k + 1 - C.q + 1) : 1);
+  const int jdone = k - 1;
+  if (C.mode == kModeBasis) {
+    if (jdone >= C.m) { C.phase = kPhaseDone; action = 3; }
+  } else if (jdone >= C.m && jdone >= 1) {
+    action = 1;
+  }
+  if (action != 3) C.phase = kPhasePass;
+  return action;
+}
+
+// Epilogue after pass kp: Algorithm 2's normalisation of R_kp, the window
+// coefficients h_{i,kp} by modified Gram-Schmidt of Algorithm 2 reproduced
+// from the inner products, the coefficients of the next pass, and the end of
+// an attempt.  With a full window (q = 0) the inner products with the older
+// vectors come from a separate phase first (epilogue_dots).
 __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, double* lds) {
   Ctrl& C = S.C;
   reduce_partials(P, S.red, lds, P.nwg);
+  if (C.q == 0 && C.kp > 1) {                 // full window: inner products first
+    if (threadIdx.x == 0) C.phase = kPhaseDots;
+    __syncthreads();
+    publish(P, S);
+    return;
+  }
   if (threadIdx.x == 0) {
-    int action = 0;
     const int k = C.kp;
     const int dlo = C.dlo;
-    const int ngd = k - dlo;
     const int p = C.p;
     const double* red = S.red;
-    const double* yk = y_row(S, k);
-    double ykr[kPM], Ky[kPM];
-#pragma unroll
-    for (int c = 0; c < kPM; ++c) ykr[c] = yk[c];
-#pragma unroll
-    for (int c = 0; c < kPM; ++c) Ky[c] = (c + 1 < kPM && c + 1 < p) ? ykr[c + 1] : 0.0;   // K y
-    double RR = red[kDotRR], UU = red[kDotUU], Ck = red[kDotCk];
-#pragma unroll
-    for (int c = 0; c < kPM; ++c) { RR += ykr[c] * ykr[c]; UU += Ky[c] * Ky[c]; Ck += ykr[c] * Ky[c]; }
-    C.matvecs += 1;
-    C.alg_bytes += pass_bytes(P, k, C.flo);
-    bool finite = isfinite(RR) && isfinite(UU) && isfinite(Ck);
-    for (int d = 0; d < ngd; ++d) finite = finite && isfinite(red[kDotG + d]) && isfinite(red[kDotC + d]);
-    const double s = sqrt(RR);
-    if (!finite) {
-      C.status = KIOPS_ERR_NONFINITE;
-      C.phase = kPhaseDone;
-      action = 3;
-    } else if (k == 1 && s == 0.0) {
-      C.beta = 0.0;                             // zero start vector: w stays zero
-      C.T_now = C.T_end;
-      C.phase = kPhaseDone;
-      action = 3;
-    } else if (k > 1 && (s == 0.0 || s <= 1e-12 * S.unorm_prev)) {
-      h_set(S, P, k, k - 1, 0.0);               // happy breakdown (Alg. 2)
-      C.breakdown = 1;
-      C.s_last = s;
-      action = (C.mode == kModeBasis) ? 3 : 2;
-      if (action == 3) C.phase = kPhaseDone;
-    } else {
-      if (k == 1) C.beta = s;
-      else h_set(S, P, k, k - 1, s);
-      C.s_last = s;
-      const double si = 1.0 / s;
-      S.sinv[k] = si;
-      P.sinv[k] = si;
-      S.unorm_prev = sqrt(UU) * si;
+    double ykr[kPM], Ky[kPM], Ck = 0.0, si = 0.0;
+    int action = step_normalise(P, S, k, ykr, Ky, Ck, si);
+    if (action < 0) {
+      const int ngd = k - dlo;
       double* gk = S.Gw[k % kRingRows];
 #pragma unroll
       for (int d = 0; d < kWinMax; ++d) gk[d] = 0.0;
@@ -490,21 +537,88 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
       }
       C.a = si;
       for (int i = dlo; i <= k; ++i) C.bw[i] = -hk[i - dlo] * S.sinv[i];
-      C.flo = dlo;
-      C.kp = k + 1;
-      C.dlo = (C.q == 0) ? 1 : ((k + 1 - C.q + 1) > 1 ? (k + 1 - C.q + 1) : 1);
-      const int jdone = k - 1;
-      if (C.mode == kModeBasis) {
-        if (jdone >= C.m) { C.phase = kPhaseDone; action = 3; }
-      } else if (jdone >= C.m && jdone >= 1) {
-        action = 1;
-      }
-      if (action != 3) C.phase = kPhasePass;
+      action = step_advance(S, k, dlo);
     }
     S.action = action;
     S.jj = k - 1;
   }
   __syncthreads();
+  const int action = S.action;
+  if (action == 1 || action == 2) attempt_end(P, S, S.jj, action == 2, lds);
+  publish(P, S);
+}
+
+// Epilogue after the inner-product phase of a full-window step (q = 0): the
+// orthogonalisation of A~ v_k against every earlier v_i by classical
+// Gram-Schmidt with one reorthogonalisation, reproduced from the inner
+// products: with c_i = <v_i, A~ v_k> and the Gram matrix G of v_1..v_k, the
+// two passes give h = c + (c - G c).  G and c live in device memory (P.G,
+// P.fullc); the sums over i run on all threads.
+__device__ __noinline__ void epilogue_dots(const KParams& P, SmallState& S, double* lds) {
+  Ctrl& C = S.C;
+  const int k = C.kp;
+  // x-parts of <R_i, R_k> and <R_i, U_k>, i < k: fixed-order sum over workgroups
+  for (int i = 1 + (int)threadIdx.x; i < k; i += kThreads) {
+    double g = 0.0, c = 0.0;
+    for (int w = 0; w < P.nwg; ++w) {
+      g += P.dpart[(int64_t)w * kDotFullStride + 2 * i];
+      c += P.dpart[(int64_t)w * kDotFullStride + 2 * i + 1];
+    }
+    P.fullc[2 * i] = g;
+    P.fullc[2 * i + 1] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ykr[kPM], Ky[kPM], Ck = 0.0, si = 0.0;
+    const int action = step_normalise(P, S, k, ykr, Ky, Ck, si);
+    for (int c = 0; c < kPM; ++c) { S.fy[c] = ykr[c]; S.fky[c] = Ky[c]; }
+    S.fsi = si;
+    S.fck = Ck;
+    S.action = action;
+    S.jj = k - 1;
+  }
+  __syncthreads();
+  if (S.action < 0) {
+    const double si = S.fsi;
+    // G(k, i) and c_i with the trailing parts, for i < k
+    for (int i = 1 + (int)threadIdx.x; i < k; i += kThreads) {
+      const double* yi = P.Y + i * kPM;
+      double yg = 0.0, yc = 0.0;
+#pragma unroll
+      for (int c = 0; c < kPM; ++c) { yg += yi[c] * S.fy[c]; yc += yi[c] * S.fky[c]; }
+      const double g = (P.fullc[2 * i] + yg) * S.sinv[i] * si;
+      P.G[k * kLdh + i] = g;
+      P.G[i * kLdh + k] = g;
+      P.coefc[i] = (P.fullc[2 * i + 1] + yc) * S.sinv[i] * si;   // c_i
+    }
+    if (threadIdx.x == 0) P.coefc[k] = S.fck * si * si;
+    __syncthreads();
+    // h_i = 2 c_i - (G c)_i, i <= k
+    for (int i = 1 + (int)threadIdx.x; i <= k; i += kThreads) {
+      double gc = 0.0;
+      for (int l = 1; l <= k; ++l) gc += (l == i ? 1.0 : P.G[i * kLdh + l]) * P.coefc[l];
+      lds[i] = 2.0 * P.coefc[i] - gc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int p = C.p;
+      for (int i = 1; i <= k; ++i) h_set(S, P, i, k, lds[i]);
+      for (int c = 0; c < kPM; ++c) {
+        double v = (c < p) ? si * S.fky[c] : 0.0;
+        if (c < p)
+          for (int i = 1; i <= k; ++i) v -= lds[i] * S.sinv[i] * P.Y[i * kPM + c];
+        const double yn = (c < p) ? v : 0.0;
+        P.Y[(k + 1) * kPM + c] = yn;
+        y_row(S, k + 1)[c] = yn;
+        C.yb_prev[c] = (c < p) ? C.nu * S.fy[c] : 0.0;
+        C.yb_cur[c] = (c < p) ? C.nu * v : 0.0;
+      }
+      C.a = si;
+      for (int i = 1; i <= k; ++i) C.bw[i] = -lds[i] * S.sinv[i];
+      S.action = step_advance(S, k, 1);
+    }
+    __syncthreads();
+  }
   const int action = S.action;
   if (action == 1 || action == 2) attempt_end(P, S, S.jj, action == 2, lds);
   publish(P, S);
@@ -548,6 +662,7 @@ __device__ inline void load_pass_ctx(const KParams& P, PassCtx<T>& c) {
     c.write_out = !(C.kp == 1 && !P.mixed);
     c.p = C.p;
     c.a = (T)C.a;
+    c.store_u = (C.q == 0);
   }
   for (int i = threadIdx.x; i < kLdh; i += kThreads) c.bw[i] = (T)C.bw[i];
   if (threadIdx.x < kPM) {
@@ -623,6 +738,63 @@ __device__ inline void gather_phase(const KParams& P, const BasisPtrs<T>& bp, do
   __syncthreads();
 }
 
+// Inner products of R_kp and U_kp (the latest pass) with every earlier basis
+// vector R_i, i < kp (full window).  Workgroup w owns elements
+// [N w / nwg, N (w+1) / nwg); a thread holds 16 elements of R_kp and U_kp at a
+// time and streams each R_i over them; wave sums accumulate in LDS per i and
+// are written as the workgroup's partials (fixed order).
+template <typename T>
+__device__ inline void dots_phase(const KParams& P, const BasisPtrs<T>& bp, double* lds) {
+  constexpr int E = 16;
+  const int kp = P.ctrl->kp;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t n0 = P.N * blockIdx.x / gridDim.x, n1 = P.N * (blockIdx.x + 1) / gridDim.x;
+  const T* U = reinterpret_cast<const T*>(P.ubuf);
+  const T* Rk = bp.get(kp);
+  double* acc = lds;                          // [kLdh][4 waves][2]
+  for (int e = t; e < kLdh * 8; e += kThreads) acc[e] = 0.0;
+  __syncthreads();
+  for (int64_t c0 = n0; c0 < n1; c0 += (int64_t)E * kThreads) {
+    double xr[E], xu[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t n = c0 + t + (int64_t)e * kThreads;
+      const bool in = n < n1;
+      xr[e] = in ? (double)Rk[n] : 0.0;
+      xu[e] = in ? (double)U[n] : 0.0;
+    }
+    for (int i = 1; i < kp; ++i) {
+      const T* Ri = bp.get(i);
+      double g = 0.0, u = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t n = c0 + t + (int64_t)e * kThreads;
+        const double r = n < n1 ? (double)Ri[n] : 0.0;
+        g = fma(r, xr[e], g);
+        u = fma(r, xu[e], u);
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        g += __shfl_xor(g, off, 64);
+        u += __shfl_xor(u, off, 64);
+      }
+      if (lane == 0) {
+        acc[i * 8 + wv * 2] += g;
+        acc[i * 8 + wv * 2 + 1] += u;
+      }
+    }
+  }
+  __syncthreads();
+  double* out = P.dpart + (int64_t)blockIdx.x * kDotFullStride;
+  for (int e = t; e < 2 * kp; e += kThreads) {
+    const int i = e >> 1, j = e & 1;
+    double v = 0.0;
+    if (i >= 1 && i < kp)
+      for (int q = 0; q < kThreads / 64; ++q) v += acc[i * 8 + q * 2 + j];
+    out[e] = v;
+  }
+  __syncthreads();
+}
+
 // Parameters live in device memory (written by the host before the launch) so
 // that no by-value kernel argument has its address taken.
 template <class Op, typename T>
@@ -667,6 +839,9 @@ kiops_solve_kernel(const KParams* __restrict__ Pp, const Op* __restrict__ opp) {
       op.pass(pctx, bp, P.w, Rout, acc, reinterpret_cast<T*>(lds));
       store_partials(P, acc, lds);
       grid_barrier(P, S, epoch, [&] { epilogue_pass(P, S, lds); });
+    } else if (phase == kPhaseDots) {
+      dots_phase<T>(P, bp, lds);
+      grid_barrier(P, S, epoch, [&] { epilogue_dots(P, S, lds); });
     } else {
       gather_phase<T>(P, bp, lds);
       grid_barrier(P, S, epoch, [&] { epilogue_gather(P, S); });

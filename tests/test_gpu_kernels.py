@@ -68,6 +68,8 @@ CASES = [
     (20, 24, 1, 1, 12, 14),
     (96, 80, 2, 4, 28, 15),
     (5, 3, 2, 2, 10, 16),
+    (40, 30, 2, 0, 24, 17),     # q = 0: full window
+    (70, 37, 3, 0, 30, 18),
 ]
 
 

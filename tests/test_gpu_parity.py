@@ -72,6 +72,26 @@ def test_ragged_grids_vs_dense_or_arnoldi(nx, ny, p, tau):
     assert rel(got, ref) <= 1e-8
 
 
+@pytest.mark.parametrize("side,p,tau", [(24, 3, 2e-2), (40, 2, 5e-3)])
+def test_full_window_q0_vs_dense(side, p, tau):
+    pr = W.adr2d_problem(side, p, tau, seed=500 + side, q=0)
+    announce(f"{side}x{side} p={p} q=0 (full Arnoldi) vs dense")
+    ref = augmented.phi_combination_dense(operators.dense(pr.op), pr.tau, pr.vectors)
+    got, st = _solve(pr)
+    assert rel(got, ref) <= 1e-8
+
+
+def test_full_window_q0_512_vs_arnoldi_and_q2():
+    pr = W.cfg2(512, 1e-3, q=0)
+    announce("512^2 p=3 tau=1e-3 q=0 vs Arnoldi oracle and the q=2 solve")
+    got, st = _solve(pr)
+    ref = phi_combination_arnoldi(operators.make_apply(pr.op), pr.tau, pr.vectors, tol_o=1e-11, m=64)
+    assert rel(got, ref) <= 1e-8
+    got2, st2 = _solve(W.cfg2(512, 1e-3, q=2))
+    announce(f"  q=0 stats {st}; q=2 stats {st2}")
+    assert rel(got2, ref) <= 1e-8
+
+
 def test_small_mmax_forces_step_size_control():
     pr = W.adr2d_problem(48, 2, 5e-2, seed=31)
     announce("48x48 m_max=24 (tau control)")

@@ -91,6 +91,15 @@ def test_3d_vs_dense(nx, ny, nz, p, tau, kappa, adv):
     assert rel(got, ref) <= 1e-8, (rel(got, ref), st)
 
 
+def test_3d_full_window_q0_vs_dense():
+    pr = _problem(12, 10, 9, 2, 2e-3, seed=91)
+    pr.q = 0
+    announce("3d 12x10x9 q=0 vs dense")
+    ref = augmented.phi_combination_dense(operators.dense(pr.op), pr.tau, pr.vectors)
+    got, st = _solve(pr)
+    assert rel(got, ref) <= 1e-8
+
+
 def test_3d_mixed_vs_dense():
     pr = _problem(16, 16, 16, 2, 1e-3, seed=77, tol=1e-6)
     announce("3d mixed 16^3")
