@@ -65,7 +65,11 @@ typedef enum {
  *                     - adv[d] (u_{i+e_d} - u_{i-e_d}) / (2 h) ] + r_i u_i
  *
  * kf = diff when kappa == NULL, else the mean of the two cells' kappa.
- * CSR: 0-based int32 row pointers (nrows+1) and column indices (nnz), float64 values.
+ * CSR: square nrows x nrows, 0-based int32 row pointers (nrows+1) and column
+ * indices (nnz), float64 values; nnz * 8 and nrows * 8 must stay below 4 GiB.
+ * A column index outside [0, nrows) or a row pointer outside [0, nnz] is read
+ * as a zero entry (the kernels bounds-check every access).
+ * Stencils: N * 8 must stay below 4 GiB.
  * All array pointers are device memory, borrowed: they must stay valid and
  * unchanged while the operator is used.
  */

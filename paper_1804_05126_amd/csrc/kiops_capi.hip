@@ -13,6 +13,7 @@
 #include "controller.h"
 #include "op_stencil2d.h"
 #include "op_stencil3d.h"
+#include "op_csr.h"
 #include "solver_kernel.h"
 
 using namespace kiops;
@@ -41,11 +42,25 @@ struct Layout {
 
 int elem_size(const kiops_operator* op) { return op->d.precision == KIOPS_MIXED ? 4 : 8; }
 
-int coef_streams(const kiops_operator* op) {
+// Per-element coefficient streams a pass reads (algorithmic bytes, in units of
+// one basis element): r and kappa for stencils; for CSR the matrix (values and
+// column indices), the row pointers, and U_{k-1} read, U_k written and R_k read
+// again by the product.
+double coef_streams(const kiops_operator* op) {
+  if (op->d.kind == KIOPS_OP_CSR) {
+    const double s = (double)elem_size(op);
+    return (double)op->d.nnz / (double)op->N * (s + 4.0) / s + 4.0 / s + 3.0;
+  }
   int c = 0;
   if (op->d.reaction) ++c;
   if (op->d.kappa) ++c;
   return c;
+}
+
+// Elements of T in the mixed-precision coefficient copies.
+size_t coef_copy_elems(const kiops_operator* op) {
+  if (op->d.kind == KIOPS_OP_CSR) return (size_t)op->d.nnz;
+  return (size_t)((op->d.reaction ? 1 : 0) + (op->d.kappa ? 1 : 0)) * (size_t)op->N;
 }
 
 // Compile-time bound on p used by the stencil passes.
@@ -68,6 +83,16 @@ const void* stencil3d_kernel(int pb) {
     case 2: return (const void*)kiops_solve_kernel<Stencil3D<T, 2>, T>;
     case 4: return (const void*)kiops_solve_kernel<Stencil3D<T, 4>, T>;
     default: return (const void*)kiops_solve_kernel<Stencil3D<T, 8>, T>;
+  }
+}
+
+template <typename T>
+const void* csr_kernel(int pb) {
+  switch (pb) {
+    case 0: return (const void*)kiops_solve_kernel<CsrOp<T, 0>, T>;
+    case 2: return (const void*)kiops_solve_kernel<CsrOp<T, 2>, T>;
+    case 4: return (const void*)kiops_solve_kernel<CsrOp<T, 4>, T>;
+    default: return (const void*)kiops_solve_kernel<CsrOp<T, 8>, T>;
   }
 }
 
@@ -99,6 +124,7 @@ const void* kernel_for(const kiops_operator* op, int p) {
   if (uses_3d(op)) return mixed ? stencil3d_kernel<float>(p_bucket(p)) : stencil3d_kernel<double>(p_bucket(p));
   if (op->d.kind == KIOPS_OP_STENCIL2D_5PT)
     return mixed ? stencil2d_kernel<float>(p_bucket(p)) : stencil2d_kernel<double>(p_bucket(p));
+  if (op->d.kind == KIOPS_OP_CSR) return mixed ? csr_kernel<float>(p_bucket(p)) : csr_kernel<double>(p_bucket(p));
   return nullptr;
 }
 
@@ -115,6 +141,7 @@ int64_t work_tiles(const kiops_operator* op) {
     const int64_t ty = (op->d.ny + Stencil2D<double, 2>::TY - 1) / Stencil2D<double, 2>::TY;
     return tx * ty;
   }
+  if (op->d.kind == KIOPS_OP_CSR) return (op->N + kThreads - 1) / kThreads;   // row blocks
   return 1;
 }
 
@@ -172,9 +199,9 @@ Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
   L.trace = take(sizeof(double) * (size_t)kTraceMax * kTraceStride);
   const size_t es = (size_t)elem_size(op);
   L.slots = take(es * (size_t)(m_max + 1) * (size_t)op->N);
-  L.ubuf = take(q == 0 ? es * (size_t)op->N : 0);
+  L.ubuf = take((q == 0 || op->d.kind == KIOPS_OP_CSR) ? es * (size_t)op->N : 0);
   L.bcopy = take(op->d.precision == KIOPS_MIXED ? es * (size_t)p * op->N : 0);
-  L.coef = take(op->d.precision == KIOPS_MIXED ? es * (size_t)coef_streams(op) * op->N : 0);
+  L.coef = take(op->d.precision == KIOPS_MIXED ? es * coef_copy_elems(op) : 0);
   L.total = off;
   return L;
 }
@@ -262,6 +289,32 @@ Stencil3D<T, PB> make_stencil3d(const kiops_operator* op, int p, const double* c
   return s;
 }
 
+template <typename T, int PB>
+CsrOp<T, PB> make_csr(const kiops_operator* op, int p, const double* const* V, char* ws, const Layout& L) {
+  const auto& d = op->d;
+  CsrOp<T, PB> s{};
+  s.N = op->N;
+  s.nnz = d.nnz;
+  s.rowptr = d.rowptr;
+  s.col = d.col;
+  s.p = p;
+  s.ubuf = reinterpret_cast<T*>(ws + L.ubuf);
+  for (int c = 0; c < kPM; ++c) s.B[c] = nullptr;
+  if (d.precision == KIOPS_MIXED) {
+    T* bc = reinterpret_cast<T*>(ws + L.bcopy);
+    for (int c = 0; c < p; ++c) s.B[c] = bc + (size_t)c * op->N;
+    s.v_src = d.val;
+    s.v_dst = reinterpret_cast<T*>(ws + L.coef);
+    s.val = s.v_dst;
+  } else {
+    for (int c = 0; c < p; ++c) s.B[c] = reinterpret_cast<const T*>(V[p - c]);
+    s.val = reinterpret_cast<const T*>(d.val);
+    s.v_src = nullptr;
+    s.v_dst = nullptr;
+  }
+  return s;
+}
+
 KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double tau, int p,
                     const double* const* V, double tol, int m_init, int q, int m_min, int m_max,
                     int max_sub, int mode, double* w) {
@@ -280,7 +333,7 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   P.T_end = tau;
   P.tol = tol;
   P.elem_bytes = (double)elem_size(op);
-  P.coef_streams = (double)coef_streams(op);
+  P.coef_streams = coef_streams(op);
   P.spin_limit = op->clock_hz * 60ull;   // a minute without progress aborts the solve
   for (int k = 0; k <= kPM; ++k) P.b[k] = (k <= p) ? V[k] : nullptr;
   P.w = w;
@@ -299,7 +352,7 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   P.coefc = reinterpret_cast<double*>(ws + L.coefc);
   P.fullc = reinterpret_cast<double*>(ws + L.fullc);
   P.dpart = reinterpret_cast<double*>(ws + L.dpart);
-  P.ubuf = q == 0 ? ws + L.ubuf : nullptr;
+  P.ubuf = (q == 0 || op->d.kind == KIOPS_OP_CSR) ? ws + L.ubuf : nullptr;
   P.partials = reinterpret_cast<double*>(ws + L.partials);
   P.expm = reinterpret_cast<double*>(ws + L.expm);
   P.trace = reinterpret_cast<double*>(ws + L.trace);
@@ -340,6 +393,18 @@ kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, c
                     : stage_op(host_block, make_stencil3d<double, 4>(op, p, V, ws, L)); break;
       default: mixed ? stage_op(host_block, make_stencil3d<float, 8>(op, p, V, ws, L))
                      : stage_op(host_block, make_stencil3d<double, 8>(op, p, V, ws, L)); break;
+    }
+  } else if (op->d.kind == KIOPS_OP_CSR) {
+    const bool mixed = op->d.precision == KIOPS_MIXED;
+    switch (p_bucket(p)) {
+      case 0: mixed ? stage_op(host_block, make_csr<float, 0>(op, p, V, ws, L))
+                    : stage_op(host_block, make_csr<double, 0>(op, p, V, ws, L)); break;
+      case 2: mixed ? stage_op(host_block, make_csr<float, 2>(op, p, V, ws, L))
+                    : stage_op(host_block, make_csr<double, 2>(op, p, V, ws, L)); break;
+      case 4: mixed ? stage_op(host_block, make_csr<float, 4>(op, p, V, ws, L))
+                    : stage_op(host_block, make_csr<double, 4>(op, p, V, ws, L)); break;
+      default: mixed ? stage_op(host_block, make_csr<float, 8>(op, p, V, ws, L))
+                     : stage_op(host_block, make_csr<double, 8>(op, p, V, ws, L)); break;
     }
   } else if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
     const bool mixed = op->d.precision == KIOPS_MIXED;
@@ -492,6 +557,9 @@ kiops_status kiops_create_operator(const kiops_operator_desc* desc, void* hip_st
       return KIOPS_ERR_INVALID_ARG;
   } else if (d.kind == KIOPS_OP_CSR) {
     if (d.nrows < 1 || d.nnz < 0 || !d.rowptr || !d.col || (!d.val && d.nnz > 0)) return KIOPS_ERR_INVALID_ARG;
+    // 32-bit byte offsets into val and the basis vectors
+    if (d.nnz * (int64_t)sizeof(double) >= ((int64_t)1 << 32) || d.nrows >= ((int64_t)1 << 29))
+      return KIOPS_ERR_INVALID_ARG;
     N = d.nrows;
   } else {
     return KIOPS_ERR_INVALID_ARG;

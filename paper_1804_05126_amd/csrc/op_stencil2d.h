@@ -36,6 +36,7 @@ struct Stencil2D {
   static constexpr int kPos = 5;                   // 4 tile positions + 1 ring position
   static constexpr int kLdsT = RX * RY + SX * SY;  // elements of T
   static constexpr int kLdsDoubles = (int)((kLdsT * sizeof(T) + 7) / 8);
+  static constexpr bool kTwoPhase = false;   // one fused pass per Krylov step
   // occupancy target: the register footprint of a tile's loads grows with PB
   static constexpr int kWavesPerEU = (PB >= 4 && sizeof(T) == 8) ? 3 : 4;
 

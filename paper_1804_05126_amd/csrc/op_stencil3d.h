@@ -34,6 +34,7 @@ struct Stencil3D {
   static constexpr int kRegionLoads = (RP + kThreads - 1) / kThreads;
   static constexpr int kLdsT = 3 * RP + 4 * RP + 3 * SP;         // elements of T
   static constexpr int kLdsDoubles = (int)((kLdsT * sizeof(T) + 7) / 8);
+  static constexpr bool kTwoPhase = false;   // one fused pass per Krylov step
   static constexpr int kWavesPerEU = 3;
 
   struct PlaneLoads {

@@ -836,7 +836,13 @@ kiops_solve_kernel(const KParams* __restrict__ Pp, const Op* __restrict__ opp) {
       DotAcc acc;
       acc.zero();
       T* Rout = bp.get_mut(pctx.kp);
-      op.pass(pctx, bp, P.w, Rout, acc, reinterpret_cast<T*>(lds));
+      if constexpr (Op::kTwoPhase) {
+        op.form(pctx, bp, P.w, Rout);
+        grid_barrier(P, S, epoch, [] {});     // R_kp complete before the product reads it
+        op.matvec(pctx, bp, Rout, acc);
+      } else {
+        op.pass(pctx, bp, P.w, Rout, acc, reinterpret_cast<T*>(lds));
+      }
       store_partials(P, acc, lds);
       grid_barrier(P, S, epoch, [&] { epilogue_pass(P, S, lds); });
     } else if (phase == kPhaseDots) {
