@@ -128,6 +128,8 @@ typedef struct {
   double arrive_max_s, arrive_mean_s;
   int64_t barriers;
   double release_max_s, release_mean_s;
+  int32_t status;          /* the solve's own status (useful for batched problems) */
+  int32_t reserved2;
 } kiops_stats;
 
 typedef struct kiops_operator kiops_operator;
@@ -167,6 +169,49 @@ kiops_status kiops_set_workspace(kiops_operator* op, void* dev_ptr, size_t bytes
 kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const double* const* V,
                                    double tol, int m_init, int q, const kiops_options* opts,
                                    double* w, kiops_stats* stats);
+
+/*
+ * Batched form: many independent phi-combinations in one persistent launch.
+ * The grid is split into groups of group_size workgroups; each group runs its
+ * share of the problems one after another (each problem is a full Algorithm 1
+ * solve on that group, with the group's own grid barrier), so problems of
+ * different sizes proceed concurrently.  Problems are assigned to groups by
+ * longest-estimated-work first.  All operators of a batch must have the same
+ * kind and precision; p may differ (0..KIOPS_P_MAX), q in 0..4.
+ */
+typedef struct {
+  kiops_operator* op;
+  double tau;                 /* >= 0 */
+  int32_t p;
+  int32_t q;
+  const double* const* V;     /* host array of p+1 device pointers */
+  double tol;                 /* > 0 */
+  int32_t m_init;
+  int32_t reserved;
+  double* w;                  /* device, N entries; may equal V[0] */
+} kiops_problem;
+
+/* Plan of a batch: workspace bytes and the number of groups.  group_size = 0
+ * picks a size from the problem sizes; otherwise it is used as given (at most
+ * the co-resident workgroups of the device). */
+kiops_status kiops_batch_plan(int count, const kiops_problem* probs, const kiops_options* opts,
+                              int group_size, size_t* workspace_bytes, int* groups, int* group_size_used);
+
+/* Run a batch.  workspace: caller-owned device memory of at least the planned
+ * bytes, 256-byte aligned.  stats: host array of count entries, or NULL.
+ * Blocks until every problem is done; returns the first non-OK status of a
+ * problem (each problem's own status is in stats[i] via its fields) or OK. */
+kiops_status kiops_phi_batch(int count, const kiops_problem* probs, const kiops_options* opts,
+                             int group_size, void* workspace, size_t workspace_bytes, void* hip_stream,
+                             kiops_stats* stats);
+
+/* Autotuner of the batched form: runs the batch once per candidate group size
+ * (candidates: host array, n entries; each the group_size of kiops_phi_batch)
+ * and returns the fastest in *best and its time in *best_ms.  The workspace
+ * must hold the largest plan among the candidates.  Outputs w are written. */
+kiops_status kiops_batch_tune(int count, const kiops_problem* probs, const kiops_options* opts,
+                              const int* candidates, int n, void* workspace, size_t workspace_bytes,
+                              void* hip_stream, int* best, double* best_ms);
 
 /* Human-readable name of a status code (static storage). */
 const char* kiops_status_string(kiops_status s);

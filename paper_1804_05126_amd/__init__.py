@@ -17,8 +17,8 @@ from typing import List, Optional, Sequence
 from . import _lib
 from ._lib import KiopsError  # noqa: F401
 
-__all__ = ["Operator", "phi_combination", "iop_basis", "small_expm", "controller_decide",
-           "KiopsError"]
+__all__ = ["Operator", "phi_combination", "phi_batch", "batch_tune", "iop_basis", "small_expm",
+           "controller_decide", "KiopsError"]
 
 
 def _torch():
@@ -167,6 +167,88 @@ def phi_combination(op: Operator, tau: float, vectors: Sequence, tol: float = 1e
     if check:
         _lib.check(status, "kiops_phi_combination")
     return w, st.as_dict(), status
+
+
+_batch_ws = {}
+
+
+def _batch_problems(problems):
+    """Marshal (op, tau, vectors, tol, m_init, q, out) entries into kiops_problem structs."""
+    torch = _torch()
+    arr = (_lib.Problem * len(problems))()
+    keep, outs = [], []
+    for i, pr in enumerate(problems):
+        op, tau, vectors = pr["op"], pr["tau"], pr["vectors"]
+        V = _vec_ptrs(vectors, op.n)
+        w = pr.get("out")
+        if w is None:
+            w = torch.empty(op.n, dtype=torch.float64, device="cuda")
+        _require_cuda_f64(w, op.n, "w")
+        arr[i].op = op._h.value
+        arr[i].tau = float(tau)
+        arr[i].p = len(vectors) - 1
+        arr[i].q = int(pr.get("q", 2))
+        arr[i].V = C.cast(V, C.POINTER(C.c_void_p))
+        arr[i].tol = float(pr.get("tol", 1e-8))
+        arr[i].m_init = int(pr.get("m_init", 10))
+        arr[i].w = _ptr(w)
+        keep.append(V)
+        outs.append(w)
+    return arr, keep, outs
+
+
+def _batch_workspace(nbytes: int):
+    torch = _torch()
+    ws = _batch_ws.get("ws")
+    if ws is None or ws.numel() < nbytes + 256:
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        _batch_ws["ws"] = ws
+    base = _ptr(ws)
+    aligned = (base + 255) // 256 * 256
+    return aligned, ws.numel() - (aligned - base)
+
+
+def phi_batch(problems: Sequence[dict], group_size: int = 0, m_min: int = 0, m_max: int = 0,
+              max_substeps: int = 0, stream=None):
+    """Batched form: every problem (a dict with op, tau, vectors and optionally
+    tol, m_init, q, out) solved in one persistent launch.  Returns
+    (list of w, list of stats dicts, status, plan) with plan = (groups, group_size)."""
+    torch = _torch()
+    lib = _lib.load()
+    arr, keep, outs = _batch_problems(problems)
+    o = _lib.Options(m_min, m_max, max_substeps, 0)
+    nbytes, groups, gs = C.c_size_t(), C.c_int(), C.c_int()
+    _lib.check(lib.kiops_batch_plan(len(problems), arr, C.byref(o), int(group_size), C.byref(nbytes),
+                                    C.byref(groups), C.byref(gs)), "kiops_batch_plan")
+    ws, wsb = _batch_workspace(nbytes.value)
+    stats = (_lib.Stats * len(problems))()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    status = lib.kiops_phi_batch(len(problems), arr, C.byref(o), int(group_size), C.c_void_p(ws), wsb,
+                                 C.c_void_p(s.cuda_stream), stats)
+    return outs, [st.as_dict() for st in stats], status, (groups.value, gs.value)
+
+
+def batch_tune(problems: Sequence[dict], candidates=(8, 16, 32, 64), m_min: int = 0, m_max: int = 0,
+               stream=None):
+    """Autotuner of the batched form: the fastest group size among candidates and its time (ms)."""
+    torch = _torch()
+    lib = _lib.load()
+    arr, keep, outs = _batch_problems(problems)
+    o = _lib.Options(m_min, m_max, 0, 0)
+    need = 0
+    for c in candidates:
+        nbytes, groups, gs = C.c_size_t(), C.c_int(), C.c_int()
+        _lib.check(lib.kiops_batch_plan(len(problems), arr, C.byref(o), int(c), C.byref(nbytes),
+                                        C.byref(groups), C.byref(gs)), "kiops_batch_plan")
+        need = max(need, nbytes.value)
+    ws, wsb = _batch_workspace(need)
+    cand = (C.c_int * len(candidates))(*candidates)
+    best, best_ms = C.c_int(), C.c_double()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _lib.check(lib.kiops_batch_tune(len(problems), arr, C.byref(o), cand, len(candidates), C.c_void_p(ws), wsb,
+                                    C.c_void_p(s.cuda_stream), C.byref(best), C.byref(best_ms)),
+               "kiops_batch_tune")
+    return best.value, best_ms.value
 
 
 def iop_basis(op: Operator, vectors: Sequence, m: int, q: int = 2):

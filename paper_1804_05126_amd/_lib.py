@@ -65,6 +65,7 @@ class Stats(C.Structure):
         ("time_expm_s", C.c_double), ("arrive_max_s", C.c_double), ("arrive_mean_s", C.c_double),
         ("barriers", C.c_int64),
         ("release_max_s", C.c_double), ("release_mean_s", C.c_double),
+        ("status", C.c_int32), ("reserved2", C.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -83,6 +84,12 @@ class CtrlIn(C.Structure):
 class CtrlOut(C.Structure):
     _fields_ = [("accept", C.c_int32), ("m_new", C.c_int32), ("branch", C.c_int32),
                 ("reserved", C.c_int32), ("tau_new", C.c_double), ("omega", C.c_double)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("op", C.c_void_p), ("tau", C.c_double), ("p", C.c_int32), ("q", C.c_int32),
+                ("V", C.POINTER(C.c_void_p)), ("tol", C.c_double), ("m_init", C.c_int32),
+                ("reserved", C.c_int32), ("w", C.c_void_p)]
 
 
 BRANCH_NAMES = {0: "breakdown", 1: "tau_reject", 2: "tau_accept", 3: "m_reject", 4: "m_accept",
@@ -107,6 +114,13 @@ SIGNATURES = [
                                    C.c_void_p]),
     ("kiops_controller_decide", C.c_int, [C.POINTER(CtrlIn), C.c_int, C.c_double, C.c_int,
                                           C.POINTER(CtrlOut)]),
+    ("kiops_batch_plan", C.c_int, [C.c_int, C.POINTER(Problem), C.POINTER(Options), C.c_int,
+                                   C.POINTER(C.c_size_t), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("kiops_phi_batch", C.c_int, [C.c_int, C.POINTER(Problem), C.POINTER(Options), C.c_int, C.c_void_p,
+                                  C.c_size_t, C.c_void_p, C.POINTER(Stats)]),
+    ("kiops_batch_tune", C.c_int, [C.c_int, C.POINTER(Problem), C.POINTER(Options), C.POINTER(C.c_int),
+                                   C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_int),
+                                   C.POINTER(C.c_double)]),
 ]
 
 _lib = None

@@ -1,0 +1,28 @@
+// Entry addresses of the solver kernels: the one-solve kernel (group = false)
+// and the group kernel of the batched and served forms (group = true), for a
+// float (mixed) or double basis and a p-bucket pb in {0, 2, 4, 8}.  Each
+// operator family lives in its own translation unit.
+#pragma once
+
+namespace kiops {
+
+const void* kernels_stencil2d(bool mixed, int pb, bool group);
+const void* kernels_stencil3d(bool mixed, int pb, bool group);
+const void* kernels_csr(bool mixed, int pb, bool group);
+
+#ifdef KIOPS_KERNEL_UNIT
+template <template <typename, int> class OP>
+const void* pick_kernel(bool mixed, int pb, bool group) {
+#define KIOPS_K(T, PB) \
+  (group ? (const void*)kiops_group_kernel<OP<T, PB>, T> : (const void*)kiops_solve_kernel<OP<T, PB>, T>)
+  switch (pb) {
+    case 0: return mixed ? KIOPS_K(float, 0) : KIOPS_K(double, 0);
+    case 2: return mixed ? KIOPS_K(float, 2) : KIOPS_K(double, 2);
+    case 4: return mixed ? KIOPS_K(float, 4) : KIOPS_K(double, 4);
+    default: return mixed ? KIOPS_K(float, 8) : KIOPS_K(double, 8);
+  }
+#undef KIOPS_K
+}
+#endif
+
+}  // namespace kiops

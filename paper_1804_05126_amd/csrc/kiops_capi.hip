@@ -8,12 +8,14 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/kiops.h"
 #include "controller.h"
 #include "op_stencil2d.h"
 #include "op_stencil3d.h"
 #include "op_csr.h"
+#include "kernel_table.h"
 #include "solver_kernel.h"
 
 using namespace kiops;
@@ -28,6 +30,25 @@ struct kiops_operator {
   void* ws;
   size_t ws_bytes;
 };
+
+namespace kiops {
+
+// Barrier words and control block before a launch (one workgroup).
+__global__ void kiops_reset_kernel(Barrier* b, Ctrl* c, unsigned* arrive, int nwg, uint64_t* arrive_t) {
+  for (int i = threadIdx.x; i < nwg; i += blockDim.x) arrive[i] = 0u;
+  for (int i = threadIdx.x; i < 3 * nwg; i += blockDim.x) arrive_t[i] = 0u;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    b->gen = 0;
+    b->abort = 0;
+    c->phase = kPhaseDone;
+    c->status = KIOPS_OK;
+    c->t_work = c->t_wait = c->t_epi = 0;
+    c->t_expm = c->t_arrive_max = c->t_arrive_mean = c->n_barriers = 0;
+    c->t_release_max = c->t_release_mean = 0;
+  }
+}
+
+}  // namespace kiops
 
 namespace {
 
@@ -66,36 +87,6 @@ size_t coef_copy_elems(const kiops_operator* op) {
 // Compile-time bound on p used by the stencil passes.
 int p_bucket(int p) { return p == 0 ? 0 : (p <= 2 ? 2 : (p <= 4 ? 4 : 8)); }
 
-template <typename T>
-const void* stencil2d_kernel(int pb) {
-  switch (pb) {
-    case 0: return (const void*)kiops_solve_kernel<Stencil2D<T, 0>, T>;
-    case 2: return (const void*)kiops_solve_kernel<Stencil2D<T, 2>, T>;
-    case 4: return (const void*)kiops_solve_kernel<Stencil2D<T, 4>, T>;
-    default: return (const void*)kiops_solve_kernel<Stencil2D<T, 8>, T>;
-  }
-}
-
-template <typename T>
-const void* stencil3d_kernel(int pb) {
-  switch (pb) {
-    case 0: return (const void*)kiops_solve_kernel<Stencil3D<T, 0>, T>;
-    case 2: return (const void*)kiops_solve_kernel<Stencil3D<T, 2>, T>;
-    case 4: return (const void*)kiops_solve_kernel<Stencil3D<T, 4>, T>;
-    default: return (const void*)kiops_solve_kernel<Stencil3D<T, 8>, T>;
-  }
-}
-
-template <typename T>
-const void* csr_kernel(int pb) {
-  switch (pb) {
-    case 0: return (const void*)kiops_solve_kernel<CsrOp<T, 0>, T>;
-    case 2: return (const void*)kiops_solve_kernel<CsrOp<T, 2>, T>;
-    case 4: return (const void*)kiops_solve_kernel<CsrOp<T, 4>, T>;
-    default: return (const void*)kiops_solve_kernel<CsrOp<T, 8>, T>;
-  }
-}
-
 // The 7-point marching pass serves 3-D operators and 2-D ones with a
 // diffusivity field (nz = 1); the 5-point tile pass serves constant-diffusivity 2-D.
 bool uses_3d(const kiops_operator* op) {
@@ -118,15 +109,17 @@ int zchunks(const kiops_operator* op, int nwg) {
   return (int)base;
 }
 
-// The kernel instantiation that serves an operator and p.
-const void* kernel_for(const kiops_operator* op, int p) {
+// Kernel of an operator for p-bucket pb: the one-solve kernel or the group kernel.
+const void* kernel_for_bucket(const kiops_operator* op, int pb, bool group) {
   const bool mixed = op->d.precision == KIOPS_MIXED;
-  if (uses_3d(op)) return mixed ? stencil3d_kernel<float>(p_bucket(p)) : stencil3d_kernel<double>(p_bucket(p));
-  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT)
-    return mixed ? stencil2d_kernel<float>(p_bucket(p)) : stencil2d_kernel<double>(p_bucket(p));
-  if (op->d.kind == KIOPS_OP_CSR) return mixed ? csr_kernel<float>(p_bucket(p)) : csr_kernel<double>(p_bucket(p));
+  if (uses_3d(op)) return kernels_stencil3d(mixed, pb, group);
+  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) return kernels_stencil2d(mixed, pb, group);
+  if (op->d.kind == KIOPS_OP_CSR) return kernels_csr(mixed, pb, group);
   return nullptr;
 }
+
+// The kernel instantiation that serves an operator and p.
+const void* kernel_for(const kiops_operator* op, int p) { return kernel_for_bucket(op, p_bucket(p), false); }
 
 int64_t work_tiles(const kiops_operator* op) {
   if (uses_3d(op)) {
@@ -365,6 +358,40 @@ void stage_op(unsigned char* host_block, const OpT& o) {
   std::memcpy(host_block + 2048, &o, sizeof(OpT));
 }
 
+// Write the operator struct of the kernel instantiation for p-bucket pb
+// (pb >= p) into blk + 2048.
+kiops_status stage_op_block(const kiops_operator* op, int p, int pb, const double* const* V, char* ws,
+                            const Layout& L, unsigned char* blk) {
+  const bool mixed = op->d.precision == KIOPS_MIXED;
+#define KIOPS_STAGE(MAKE)                                                                          \
+  switch (pb) {                                                                                    \
+    case 0: mixed ? stage_op(blk, MAKE<float, 0>(op, p, V, ws, L)) : stage_op(blk, MAKE<double, 0>(op, p, V, ws, L)); break; \
+    case 2: mixed ? stage_op(blk, MAKE<float, 2>(op, p, V, ws, L)) : stage_op(blk, MAKE<double, 2>(op, p, V, ws, L)); break; \
+    case 4: mixed ? stage_op(blk, MAKE<float, 4>(op, p, V, ws, L)) : stage_op(blk, MAKE<double, 4>(op, p, V, ws, L)); break; \
+    default: mixed ? stage_op(blk, MAKE<float, 8>(op, p, V, ws, L)) : stage_op(blk, MAKE<double, 8>(op, p, V, ws, L)); break; \
+  }
+  if (uses_3d(op)) {
+    KIOPS_STAGE(make_stencil3d)
+  } else if (op->d.kind == KIOPS_OP_CSR) {
+    KIOPS_STAGE(make_csr)
+  } else if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
+    KIOPS_STAGE(make_stencil2d)
+  } else {
+    return KIOPS_ERR_UNSUPPORTED;
+  }
+#undef KIOPS_STAGE
+  return KIOPS_OK;
+}
+
+// Group-kernel instantiation (batched and served forms) for p-bucket pb.
+const void* group_kernel_for(const kiops_operator* op, int pb) { return kernel_for_bucket(op, pb, true); }
+
+// Kernel family of an operator: instances of one batch must share it.
+int op_family(const kiops_operator* op) {
+  const int k = uses_3d(op) ? 1 : (op->d.kind == KIOPS_OP_CSR ? 2 : 0);
+  return k * 2 + (op->d.precision == KIOPS_MIXED ? 1 : 0);
+}
+
 // Launch one persistent solve and wait for its control block.
 kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, const double* const* V,
                        Ctrl* host_ctrl, unsigned* host_abort) {
@@ -382,45 +409,8 @@ kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, c
   void* dOp = ws + L.params + 2048;
   const void* fn = kernel_for(op, p);
   if (!fn) return KIOPS_ERR_UNSUPPORTED;
-  if (uses_3d(op)) {
-    const bool mixed = op->d.precision == KIOPS_MIXED;
-    switch (p_bucket(p)) {
-      case 0: mixed ? stage_op(host_block, make_stencil3d<float, 0>(op, p, V, ws, L))
-                    : stage_op(host_block, make_stencil3d<double, 0>(op, p, V, ws, L)); break;
-      case 2: mixed ? stage_op(host_block, make_stencil3d<float, 2>(op, p, V, ws, L))
-                    : stage_op(host_block, make_stencil3d<double, 2>(op, p, V, ws, L)); break;
-      case 4: mixed ? stage_op(host_block, make_stencil3d<float, 4>(op, p, V, ws, L))
-                    : stage_op(host_block, make_stencil3d<double, 4>(op, p, V, ws, L)); break;
-      default: mixed ? stage_op(host_block, make_stencil3d<float, 8>(op, p, V, ws, L))
-                     : stage_op(host_block, make_stencil3d<double, 8>(op, p, V, ws, L)); break;
-    }
-  } else if (op->d.kind == KIOPS_OP_CSR) {
-    const bool mixed = op->d.precision == KIOPS_MIXED;
-    switch (p_bucket(p)) {
-      case 0: mixed ? stage_op(host_block, make_csr<float, 0>(op, p, V, ws, L))
-                    : stage_op(host_block, make_csr<double, 0>(op, p, V, ws, L)); break;
-      case 2: mixed ? stage_op(host_block, make_csr<float, 2>(op, p, V, ws, L))
-                    : stage_op(host_block, make_csr<double, 2>(op, p, V, ws, L)); break;
-      case 4: mixed ? stage_op(host_block, make_csr<float, 4>(op, p, V, ws, L))
-                    : stage_op(host_block, make_csr<double, 4>(op, p, V, ws, L)); break;
-      default: mixed ? stage_op(host_block, make_csr<float, 8>(op, p, V, ws, L))
-                     : stage_op(host_block, make_csr<double, 8>(op, p, V, ws, L)); break;
-    }
-  } else if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
-    const bool mixed = op->d.precision == KIOPS_MIXED;
-    switch (p_bucket(p)) {
-      case 0: mixed ? stage_op(host_block, make_stencil2d<float, 0>(op, p, V, ws, L))
-                    : stage_op(host_block, make_stencil2d<double, 0>(op, p, V, ws, L)); break;
-      case 2: mixed ? stage_op(host_block, make_stencil2d<float, 2>(op, p, V, ws, L))
-                    : stage_op(host_block, make_stencil2d<double, 2>(op, p, V, ws, L)); break;
-      case 4: mixed ? stage_op(host_block, make_stencil2d<float, 4>(op, p, V, ws, L))
-                    : stage_op(host_block, make_stencil2d<double, 4>(op, p, V, ws, L)); break;
-      default: mixed ? stage_op(host_block, make_stencil2d<float, 8>(op, p, V, ws, L))
-                     : stage_op(host_block, make_stencil2d<double, 8>(op, p, V, ws, L)); break;
-    }
-  } else {
-    return KIOPS_ERR_UNSUPPORTED;
-  }
+  kiops_status st = stage_op_block(op, p, p_bucket(p), V, ws, L, host_block);
+  if (st != KIOPS_OK) return st;
   if (!hip_ok(hipMemcpyAsync(dP, host_block, sizeof(host_block), hipMemcpyHostToDevice, op->stream)))
     return KIOPS_ERR_DEVICE;
   {
@@ -460,6 +450,7 @@ void fill_stats(const Ctrl& c, int nwg, double clock_hz, kiops_stats* st) {
   st->t_reached = c.T_now;
   st->alg_bytes = c.alg_bytes;
   st->beta_last = c.beta;
+  st->status = c.status;
 }
 
 kiops_status check_vectors(const kiops_operator* op, int p, const double* const* V, const double* w) {
@@ -520,6 +511,195 @@ __global__ void small_expm_kernel(const double* Hs, int n, double tau, double* F
   const int slot = wg_expm(scratch, n, eta, lds);
   const double* R = scratch + (size_t)slot * kExpmSlot;
   for (int e = threadIdx.x; e < n * n; e += kThreads) F[e] = R[(e / n) * kExpmLd + (e % n)];
+}
+
+// ---------------------------------------------------------------- batches
+
+struct BatchPlan {
+  int gs = 0, ng = 0, pb = 0, m_min = 0, m_max = 0, max_sub = 0;
+  const void* fn = nullptr;
+  std::vector<int> group_of;            // problem -> group
+  std::vector<std::vector<int>> members;
+  std::vector<size_t> group_off;        // group workspace offsets
+  size_t ctrl_off = 0, block_off = 0, queue_off = 0, total = 0;
+};
+
+size_t ctrl_stride() { return align_up(sizeof(Ctrl)); }
+
+// Work estimate of a problem for the assignment: N times (1 + tau ||A||_1),
+// ||A||_1 bounded from the operator description.
+double work_estimate(const kiops_problem& pr) {
+  const kiops_operator_desc& d = pr.op->d;
+  double a = 1.0;
+  if (d.kind != KIOPS_OP_CSR) {
+    const int dims = d.nz > 1 ? 3 : 2;
+    const double kap = d.kappa ? 1.0 : std::fabs(d.diff);
+    a += 4.0 * dims * kap / (d.h * d.h) + (std::fabs(d.adv[0]) + std::fabs(d.adv[1]) + std::fabs(d.adv[2])) / d.h;
+  } else {
+    a += 10.0 * (double)d.nnz / (double)std::max<int64_t>(1, d.nrows);
+  }
+  return (double)pr.op->N * (1.0 + pr.tau * a);
+}
+
+kiops_status plan_batch(int count, const kiops_problem* probs, const kiops_options* opts, int group_size,
+                        BatchPlan& B) {
+  if (count < 1 || !probs) return KIOPS_ERR_INVALID_ARG;
+  int pmax = 0;
+  for (int i = 0; i < count; ++i) {
+    const kiops_problem& pr = probs[i];
+    if (!pr.op || !(pr.tau >= 0.0) || !std::isfinite(pr.tau) || !(pr.tol > 0.0) || !std::isfinite(pr.tol) ||
+        pr.m_init < 1 || pr.q < 0 || pr.q > 8)
+      return KIOPS_ERR_INVALID_ARG;
+    kiops_status s = check_vectors(pr.op, pr.p, pr.V, pr.w);
+    if (s != KIOPS_OK) return s;
+    if (pr.q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
+    if (op_family(pr.op) != op_family(probs[0].op)) return KIOPS_ERR_UNSUPPORTED;
+    pmax = std::max(pmax, pr.p);
+  }
+  resolve_options(probs[0].op, opts, &B.m_min, &B.m_max, &B.max_sub);
+  if (B.m_max > KIOPS_M_MAX_LIMIT || B.m_min > B.m_max || B.m_min < 1) return KIOPS_ERR_INVALID_ARG;
+  B.pb = p_bucket(pmax);
+  B.fn = group_kernel_for(probs[0].op, B.pb);
+  if (!B.fn) return KIOPS_ERR_UNSUPPORTED;
+  int per_cu = 0;
+  if (!hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, B.fn, kThreads, 0)) || per_cu < 1)
+    return KIOPS_ERR_DEVICE;
+  const int total = per_cu * probs[0].op->cus;
+  int gs = group_size;
+  if (gs <= 0) {
+    // about a quarter of the median problem's work tiles, a power of two in [8, 64]
+    std::vector<int64_t> tiles(count);
+    for (int i = 0; i < count; ++i) tiles[i] = work_tiles(probs[i].op);
+    std::nth_element(tiles.begin(), tiles.begin() + count / 2, tiles.end());
+    const int64_t want = std::max<int64_t>(1, tiles[count / 2] / 4);
+    gs = 8;
+    while (gs < 64 && gs < want) gs *= 2;
+  }
+  if (gs > total) return KIOPS_ERR_INVALID_ARG;
+  B.gs = gs;
+  B.ng = std::min(total / gs, count);
+  // longest estimated work first, each to the least-loaded group
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::vector<double> est(count);
+  for (int i = 0; i < count; ++i) est[i] = work_estimate(probs[i]);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return est[a] > est[b]; });
+  std::vector<double> load(B.ng, 0.0);
+  B.group_of.assign(count, 0);
+  B.members.assign(B.ng, {});
+  for (int i : order) {
+    int g = 0;
+    for (int h = 1; h < B.ng; ++h)
+      if (load[h] < load[g] || (load[h] == load[g] && B.members[h].size() < B.members[g].size())) g = h;
+    if ((int)B.members[g].size() >= kGroupQueueLen) return KIOPS_ERR_UNSUPPORTED;
+    B.group_of[i] = g;
+    B.members[g].push_back(i);
+    load[g] += est[i];
+  }
+  // workspace: one region per group (the largest layout among its problems;
+  // the barrier words sit at the same offsets in every layout of the group),
+  // then per-problem control blocks, parameter blocks and the group queues
+  size_t off = 0;
+  B.group_off.assign(B.ng, 0);
+  for (int g = 0; g < B.ng; ++g) {
+    size_t need = 0;
+    for (int i : B.members[g]) {
+      const Layout L = make_layout(probs[i].op, probs[i].p, probs[i].q, B.m_max, gs);
+      need = std::max(need, L.total);
+    }
+    B.group_off[g] = off;
+    off = align_up(off + need);
+  }
+  B.ctrl_off = off;
+  off = align_up(off + ctrl_stride() * count);
+  B.block_off = off;
+  off = align_up(off + (size_t)4096 * count);
+  B.queue_off = off;
+  off = align_up(off + sizeof(GroupQueue) * B.ng);
+  B.total = off;
+  return KIOPS_OK;
+}
+
+kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B, char* ws, hipStream_t stream,
+                       kiops_stats* stats, double* ms_out) {
+  std::vector<unsigned char> blocks((size_t)4096 * count, 0);
+  std::vector<unsigned char> ctrls(ctrl_stride() * count, 0);
+  for (int i = 0; i < count; ++i) {
+    Ctrl c{};
+    c.phase = kPhaseDone;
+    c.status = KIOPS_ERR_DEVICE;   // until the solve publishes its own
+    std::memcpy(ctrls.data() + ctrl_stride() * i, &c, sizeof(Ctrl));
+  }
+  std::vector<GroupQueue> queues(B.ng);
+  const uint64_t clock_hz = probs[0].op->clock_hz;
+  for (int g = 0; g < B.ng; ++g) {
+    GroupQueue& Q = queues[g];
+    std::memset(&Q, 0, sizeof(GroupQueue));
+    Q.tail = (unsigned)B.members[g].size();
+    Q.closed = 1;
+    Q.idle_limit = clock_hz * 60ull;
+    char* base = ws + B.group_off[g];
+    for (size_t e = 0; e < B.members[g].size(); ++e) {
+      const int i = B.members[g][e];
+      const kiops_problem& pr = probs[i];
+      const Layout L = make_layout(pr.op, pr.p, pr.q, B.m_max, B.gs);
+      KParams P = make_params(pr.op, L, base, pr.tau, pr.p, pr.V, pr.tol, pr.m_init, pr.q, B.m_min, B.m_max,
+                              B.max_sub, kModeSolve, pr.w);
+      P.ctrl = reinterpret_cast<Ctrl*>(ws + B.ctrl_off + ctrl_stride() * i);
+      unsigned char* blk = blocks.data() + (size_t)4096 * i;
+      std::memcpy(blk, &P, sizeof(KParams));
+      kiops_status s = stage_op_block(pr.op, pr.p, B.pb, pr.V, base, L, blk);
+      if (s != KIOPS_OK) return s;
+      Q.blocks[e] = reinterpret_cast<const unsigned char*>(ws + B.block_off + (size_t)4096 * i);
+    }
+    // the group's barrier words: zero (same offsets for every layout of the group)
+    const Layout L0 = make_layout(probs[B.members[g][0]].op, probs[B.members[g][0]].p,
+                                  probs[B.members[g][0]].q, B.m_max, B.gs);
+    if (!hip_ok(hipMemsetAsync(base + L0.bar, 0, L0.H - L0.bar, stream))) return KIOPS_ERR_DEVICE;
+  }
+  if (!hip_ok(hipMemcpyAsync(ws + B.ctrl_off, ctrls.data(), ctrls.size(), hipMemcpyHostToDevice, stream)) ||
+      !hip_ok(hipMemcpyAsync(ws + B.block_off, blocks.data(), blocks.size(), hipMemcpyHostToDevice, stream)) ||
+      !hip_ok(hipMemcpyAsync(ws + B.queue_off, queues.data(), sizeof(GroupQueue) * B.ng, hipMemcpyHostToDevice,
+                             stream)))
+    return KIOPS_ERR_DEVICE;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms_out) {
+    if (!hip_ok(hipEventCreate(&e0)) || !hip_ok(hipEventCreate(&e1))) return KIOPS_ERR_DEVICE;
+    hipEventRecord(e0, stream);
+  }
+  GroupQueue* dq = reinterpret_cast<GroupQueue*>(ws + B.queue_off);
+  int gs = B.gs;
+  void* args[] = {&dq, &gs};
+  if (!hip_ok(hipLaunchCooperativeKernel(B.fn, dim3(B.ng * B.gs), dim3(kThreads), args, 0, stream)))
+    return KIOPS_ERR_DEVICE;
+  if (ms_out) hipEventRecord(e1, stream);
+  if (!hip_ok(hipMemcpyAsync(ctrls.data(), ws + B.ctrl_off, ctrls.size(), hipMemcpyDeviceToHost, stream)))
+    return KIOPS_ERR_DEVICE;
+  std::vector<unsigned> aborts(B.ng, 0);
+  for (int g = 0; g < B.ng; ++g) {
+    const Layout L0 = make_layout(probs[B.members[g][0]].op, probs[B.members[g][0]].p,
+                                  probs[B.members[g][0]].q, B.m_max, B.gs);
+    const Barrier* bar = reinterpret_cast<const Barrier*>(ws + B.group_off[g] + L0.bar);
+    if (!hip_ok(hipMemcpyAsync(&aborts[g], &bar->abort, sizeof(unsigned), hipMemcpyDeviceToHost, stream)))
+      return KIOPS_ERR_DEVICE;
+  }
+  if (!hip_ok(hipStreamSynchronize(stream))) return KIOPS_ERR_DEVICE;
+  if (ms_out) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    *ms_out = ms;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+  }
+  kiops_status first = KIOPS_OK;
+  for (int i = 0; i < count; ++i) {
+    Ctrl c;
+    std::memcpy(&c, ctrls.data() + ctrl_stride() * i, sizeof(Ctrl));
+    if (aborts[B.group_of[i]] && c.status == KIOPS_OK) c.status = KIOPS_ERR_DEVICE;
+    if (stats) fill_stats(c, B.gs, (double)clock_hz, &stats[i]);
+    if (first == KIOPS_OK && c.status != KIOPS_OK) first = (kiops_status)c.status;
+  }
+  return first;
 }
 
 }  // namespace
@@ -705,6 +885,52 @@ kiops_status kiops_small_expm(int n, const double* Hs, double tau, double* F, do
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   hipLaunchKernelGGL(small_expm_kernel, dim3(1), dim3(kThreads), 0, st, Hs, n, tau, F, scratch);
   if (!hip_ok(hipGetLastError()) || !hip_ok(hipStreamSynchronize(st))) return KIOPS_ERR_DEVICE;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_batch_plan(int count, const kiops_problem* probs, const kiops_options* opts, int group_size,
+                              size_t* workspace_bytes, int* groups, int* group_size_used) {
+  BatchPlan B;
+  kiops_status s = plan_batch(count, probs, opts, group_size, B);
+  if (s != KIOPS_OK) return s;
+  if (workspace_bytes) *workspace_bytes = B.total;
+  if (groups) *groups = B.ng;
+  if (group_size_used) *group_size_used = B.gs;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_phi_batch(int count, const kiops_problem* probs, const kiops_options* opts, int group_size,
+                             void* workspace, size_t workspace_bytes, void* hip_stream, kiops_stats* stats) {
+  BatchPlan B;
+  kiops_status s = plan_batch(count, probs, opts, group_size, B);
+  if (s != KIOPS_OK) return s;
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return KIOPS_ERR_INVALID_ARG;
+  if (workspace_bytes < B.total) return KIOPS_ERR_OUT_OF_MEMORY;
+  if (stats) std::memset(stats, 0, sizeof(kiops_stats) * count);
+  return run_batch(count, probs, B, reinterpret_cast<char*>(workspace), reinterpret_cast<hipStream_t>(hip_stream),
+                   stats, nullptr);
+}
+
+kiops_status kiops_batch_tune(int count, const kiops_problem* probs, const kiops_options* opts,
+                              const int* candidates, int n, void* workspace, size_t workspace_bytes,
+                              void* hip_stream, int* best, double* best_ms) {
+  if (!candidates || n < 1 || !best) return KIOPS_ERR_INVALID_ARG;
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return KIOPS_ERR_INVALID_ARG;
+  double bms = 0.0;
+  int bgs = 0;
+  for (int c = 0; c < n; ++c) {
+    BatchPlan B;
+    kiops_status s = plan_batch(count, probs, opts, candidates[c], B);
+    if (s != KIOPS_OK) return s;
+    if (workspace_bytes < B.total) return KIOPS_ERR_OUT_OF_MEMORY;
+    double ms = 0.0;
+    s = run_batch(count, probs, B, reinterpret_cast<char*>(workspace), reinterpret_cast<hipStream_t>(hip_stream),
+                  nullptr, &ms);
+    if (s != KIOPS_OK) return s;
+    if (bgs == 0 || ms < bms) { bms = ms; bgs = B.gs; }
+  }
+  *best = bgs;
+  if (best_ms) *best_ms = bms;
   return KIOPS_OK;
 }
 

@@ -42,8 +42,8 @@ struct CsrOp {
   }
 
   __device__ void row_range(int64_t& r0, int64_t& r1) const {
-    r0 = N * (int64_t)blockIdx.x / gridDim.x;
-    r1 = N * (int64_t)(blockIdx.x + 1) / gridDim.x;
+    r0 = N * (int64_t)vblock() / vgrid();
+    r1 = N * (int64_t)(vblock() + 1) / vgrid();
   }
 
   // R_k from U_{k-1} and the window (for k = 1: R_1 = w, copied in mixed mode)
@@ -80,8 +80,10 @@ struct CsrOp {
     const __amdgpu_buffer_rsrc_t rsC = make_rsrc(col, (uint64_t)nnz * 4);
     const __amdgpu_buffer_rsrc_t rsV = make_rsrc(val, (uint64_t)nnz * sizeof(T));
     for (int64_t n = r0 + threadIdx.x; n < r1; n += kThreads) {
-      const int j0 = (int)__builtin_amdgcn_raw_buffer_load_b32(rsP, (uint32_t)n * 4u, 0, 0);
-      const int j1 = (int)__builtin_amdgcn_raw_buffer_load_b32(rsP, (uint32_t)(n + 1) * 4u, 0, 0);
+      int j0 = (int)__builtin_amdgcn_raw_buffer_load_b32(rsP, (uint32_t)n * 4u, 0, 0);
+      int j1 = (int)__builtin_amdgcn_raw_buffer_load_b32(rsP, (uint32_t)(n + 1) * 4u, 0, 0);
+      j0 = j0 < 0 ? 0 : (j0 > (int)nnz ? (int)nnz : j0);   // a row is a sub-range of [0, nnz)
+      j1 = j1 < j0 ? j0 : (j1 > (int)nnz ? (int)nnz : j1);
       T U = T(0);
       for (int j = j0; j < j1; ++j) {
         const uint32_t cj = __builtin_amdgcn_raw_buffer_load_b32(rsC, (uint32_t)j * 4u, 0, 0);

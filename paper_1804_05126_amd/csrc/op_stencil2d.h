@@ -98,12 +98,12 @@ struct Stencil2D {
     // the tiles in flight on an XCD are horizontal and vertical neighbours and
     // their halos and rings are served by that XCD's L2.  (Grids smaller than
     // 8 use as many bands as workgroups.)
-    const int nband = (int)gridDim.x < kXcds ? (int)gridDim.x : kXcds;
-    const int band = (int)blockIdx.x % nband;
-    const int nloc = ((int)gridDim.x - band + nband - 1) / nband;   // workgroups of this band
+    const int nband = vgrid() < kXcds ? vgrid() : kXcds;
+    const int band = vblock() % nband;
+    const int nloc = (vgrid() - band + nband - 1) / nband;   // workgroups of this band
     const int t_lo = (int)((int64_t)ntiles * band / nband);
     const int t_hi = (int)((int64_t)ntiles * (band + 1) / nband);
-    for (int tile = t_lo + (int)blockIdx.x / nband; tile < t_hi; tile += nloc) {
+    for (int tile = t_lo + vblock() / nband; tile < t_hi; tile += nloc) {
       const int x0 = (tile % tiles_x) * TX;
       const int y0 = (tile / tiles_x) * TY;
       // ---- issue every load of the tile

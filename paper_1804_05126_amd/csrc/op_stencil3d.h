@@ -128,12 +128,12 @@ struct Stencil3D {
 
     // XCD-aware order (as in the 2-D stencil): one contiguous band of the item
     // sequence per XCD, swept together by the band's workgroups
-    const int nband = (int)gridDim.x < kXcds ? (int)gridDim.x : kXcds;
-    const int band = (int)blockIdx.x % nband;
-    const int nloc = ((int)gridDim.x - band + nband - 1) / nband;
+    const int nband = vgrid() < kXcds ? vgrid() : kXcds;
+    const int band = vblock() % nband;
+    const int nloc = (vgrid() - band + nband - 1) / nband;
     const int i_lo = (int)((int64_t)nitems * band / nband);
     const int i_hi = (int)((int64_t)nitems * (band + 1) / nband);
-    for (int item = i_lo + (int)blockIdx.x / nband; item < i_hi; item += nloc) {
+    for (int item = i_lo + vblock() / nband; item < i_hi; item += nloc) {
       const int tx = item % tiles_x;
       const int rest = item / tiles_x;
       const int x0 = tx * TX;

@@ -28,6 +28,20 @@ enum Phase : int32_t { kPhasePass = 0, kPhaseGather = 1, kPhaseDone = 2, kPhaseD
 constexpr int kDotFullStride = 2 * kLdh;            // full-window inner products per workgroup
 enum Mode : int32_t { kModeSolve = 0, kModeBasis = 1 };
 
+// The solve a workgroup works on: its index among that solve's workgroups and
+// their number (the whole grid for a single solve; one group of workgroups of
+// a batched or served launch).  Set once per workgroup at kernel entry.
+__shared__ int kiops_vgrid[2];
+__device__ __forceinline__ int vblock() { return kiops_vgrid[0]; }
+__device__ __forceinline__ int vgrid() { return kiops_vgrid[1]; }
+__device__ __forceinline__ void set_vgrid(int b, int n) {
+  if (threadIdx.x == 0) {
+    kiops_vgrid[0] = b;
+    kiops_vgrid[1] = n;
+  }
+  __syncthreads();
+}
+
 // Small solver state, in the workspace.  Written only inside epilogues.
 struct Ctrl {
   // ---- what the workgroups do next
@@ -102,6 +116,21 @@ struct KParams {
   double* partials;            // nwg x ndot_stride
   double* expm;                // small-exponential scratch
   double* trace;               // kTraceMax x kTraceStride
+};
+
+// Work queue of one group of workgroups (batched and served launches).  The
+// host publishes entry e by storing its parameter block pointer at
+// blocks[e % kGroupQueueLen] and then tail = e + 1; the group stores done =
+// e + 1 when that solve has finished (its control block is then final).
+constexpr int kGroupQueueLen = 256;
+struct GroupQueue {
+  unsigned tail;            // entries published (host)
+  unsigned closed;          // no more entries will come (host)
+  unsigned done;            // entries finished (device)
+  unsigned pad0;
+  uint64_t idle_limit;      // wall-clock ticks a group waits for an entry
+  uint64_t pad1[13];        // one 128-byte line for the words above
+  const unsigned char* blocks[kGroupQueueLen];
 };
 
 }  // namespace kiops

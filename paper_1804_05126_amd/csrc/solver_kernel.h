@@ -81,18 +81,18 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
   // The workgroup's stores are ordered before thread 0's agent-scope release
   // (one L2 write-back per workgroup rather than one per wave).
   __syncthreads();
-  if (blockIdx.x != 0) {
+  if (vblock() != 0) {
     if (threadIdx.x == 0) {
-      if (P.profile) P.arrive_t[blockIdx.x] = (uint64_t)wall_clock64();
+      if (P.profile) P.arrive_t[vblock()] = (uint64_t)wall_clock64();
       __threadfence();
-      __hip_atomic_store(&P.arrive[blockIdx.x], epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
+      __hip_atomic_store(&P.arrive[vblock()], epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
       const uint64_t t0 = (uint64_t)wall_clock64();
       for (unsigned spins = 1;; ++spins) {
         if (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) break;
         __builtin_amdgcn_s_sleep(2);
         if ((spins & 63u) == 0 && spin_expired(b, t0, P.spin_limit)) break;
       }
-      if (P.profile) P.arrive_t[P.nwg + blockIdx.x] = (uint64_t)wall_clock64();
+      if (P.profile) P.arrive_t[P.nwg + vblock()] = (uint64_t)wall_clock64();
       __threadfence();
     }
     __syncthreads();
@@ -683,13 +683,13 @@ __device__ inline void store_partials(const KParams& P, const DotAcc& acc, doubl
     packed[kDotC + d] = acc.C[d];
   }
   packed[kDotCk] = acc.Ck;
-  block_sum(packed, kDotSlots, lds, P.partials + (int64_t)blockIdx.x * P.ndot_stride);
+  block_sum(packed, kDotSlots, lds, P.partials + (int64_t)vblock() * P.ndot_stride);
 }
 
 template <class Op, typename T>
 __device__ inline void setup_phase(const KParams& P, const Op& op, T* bcopy, double* lds) {
-  const int64_t gt = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t gs = (int64_t)gridDim.x * kThreads;
+  const int64_t gt = (int64_t)vblock() * kThreads + threadIdx.x;
+  const int64_t gs = (int64_t)vgrid() * kThreads;
   for (int64_t e = gt; e < (int64_t)kLdh * kLdh; e += gs) { P.H[e] = 0.0; P.G[e] = 0.0; }
   double sums[kDotSlots];
 #pragma unroll
@@ -707,7 +707,7 @@ __device__ inline void setup_phase(const KParams& P, const Op& op, T* bcopy, dou
     }
   }
   op.setup_coefficients(P, gt, gs);
-  block_sum(sums, kDotSlots, lds, P.partials + (int64_t)blockIdx.x * P.ndot_stride);
+  block_sum(sums, kDotSlots, lds, P.partials + (int64_t)vblock() * P.ndot_stride);
 }
 
 // Gather w <- sum_i cg[i] R_i (R_1 = w).
@@ -717,8 +717,8 @@ __device__ inline void gather_phase(const KParams& P, const BasisPtrs<T>& bp, do
   const int jg = C.jg;
   for (int i = threadIdx.x; i <= jg; i += kThreads) lds[i] = C.cg[i];
   __syncthreads();
-  const int64_t gt = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t gs = (int64_t)gridDim.x * kThreads;
+  const int64_t gt = (int64_t)vblock() * kThreads + threadIdx.x;
+  const int64_t gs = (int64_t)vgrid() * kThreads;
   for (int64_t n = gt; n < P.N; n += gs) {
     double acc = lds[1] * P.w[n];
     int i = 2;
@@ -748,7 +748,7 @@ __device__ inline void dots_phase(const KParams& P, const BasisPtrs<T>& bp, doub
   constexpr int E = 16;
   const int kp = P.ctrl->kp;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int64_t n0 = P.N * blockIdx.x / gridDim.x, n1 = P.N * (blockIdx.x + 1) / gridDim.x;
+  const int64_t n0 = P.N * vblock() / vgrid(), n1 = P.N * (vblock() + 1) / vgrid();
   const T* U = reinterpret_cast<const T*>(P.ubuf);
   const T* Rk = bp.get(kp);
   double* acc = lds;                          // [kLdh][4 waves][2]
@@ -784,7 +784,7 @@ __device__ inline void dots_phase(const KParams& P, const BasisPtrs<T>& bp, doub
     }
   }
   __syncthreads();
-  double* out = P.dpart + (int64_t)blockIdx.x * kDotFullStride;
+  double* out = P.dpart + (int64_t)vblock() * kDotFullStride;
   for (int e = t; e < 2 * kp; e += kThreads) {
     const int i = e >> 1, j = e & 1;
     double v = 0.0;
@@ -795,32 +795,24 @@ __device__ inline void dots_phase(const KParams& P, const BasisPtrs<T>& bp, doub
   __syncthreads();
 }
 
-// Parameters live in device memory (written by the host before the launch) so
-// that no by-value kernel argument has its address taken.
+// One solve (Algorithm 1) on the workgroups of the current virtual grid.
+// `epoch` is the grid-barrier epoch of this group of workgroups; it keeps
+// counting across the solves a group runs one after another.
 template <class Op, typename T>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Op::kWavesPerEU, 8)))
-kiops_solve_kernel(const KParams* __restrict__ Pp, const Op* __restrict__ opp) {
-  const KParams& P = *Pp;
-  const Op& op = *opp;
-  // pass tiles (size set by the operator) / small-exponential and reduction staging
-  constexpr int kLds = Op::kLdsDoubles > kLdsDoubles ? Op::kLdsDoubles : kLdsDoubles;
-  __shared__ double lds[kLds];
-  __shared__ PassCtx<T> pctx;
-  __shared__ SmallState S;       // used by workgroup 0 only
-  __shared__ int s_phase;
+__device__ inline void solve_instance(const KParams& P, const Op& op, SmallState& S, PassCtx<T>& pctx,
+                                      double* lds, int& s_phase, unsigned& epoch) {
   T* bcopy = reinterpret_cast<T*>(P.bcopy);
   BasisPtrs<T> bp;
   bp.R1 = P.mixed ? reinterpret_cast<const T*>(P.slots) : reinterpret_cast<const T*>(P.w);
   bp.slots = reinterpret_cast<T*>(P.slots);
   bp.N = P.N;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vblock() == 0 && threadIdx.x == 0) {
     S.C.t_work = S.C.t_wait = S.C.t_epi = 0;
     S.C.t_expm = S.C.t_arrive_max = S.C.t_arrive_mean = S.C.n_barriers = 0;
     S.C.t_release_max = S.C.t_release_mean = 0;
     S.C.t_last = (uint64_t)wall_clock64();
   }
 
-  unsigned epoch = 0;
   setup_phase<Op, T>(P, op, bcopy, lds);
   grid_barrier(P, S, epoch, [&] { epilogue_setup(P, S, lds); });
 
@@ -855,17 +847,67 @@ kiops_solve_kernel(const KParams* __restrict__ Pp, const Op* __restrict__ opp) {
   }
 }
 
-__global__ void kiops_reset_kernel(Barrier* b, Ctrl* c, unsigned* arrive, int nwg, uint64_t* arrive_t) {
-  for (int i = threadIdx.x; i < nwg; i += blockDim.x) arrive[i] = 0u;
-  for (int i = threadIdx.x; i < 3 * nwg; i += blockDim.x) arrive_t[i] = 0u;
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    b->gen = 0;
-    b->abort = 0;
-    c->phase = kPhaseDone;
-    c->status = KIOPS_OK;
-    c->t_work = c->t_wait = c->t_epi = 0;
-    c->t_expm = c->t_arrive_max = c->t_arrive_mean = c->n_barriers = 0;
-    c->t_release_max = c->t_release_mean = 0;
+// One solve on the whole grid.  Parameters live in device memory (written by
+// the host before the launch) so that no by-value kernel argument has its
+// address taken.
+template <class Op, typename T>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Op::kWavesPerEU, 8)))
+kiops_solve_kernel(const KParams* __restrict__ Pp, const Op* __restrict__ opp) {
+  // pass tiles (size set by the operator) / small-exponential and reduction staging
+  constexpr int kLds = Op::kLdsDoubles > kLdsDoubles ? Op::kLdsDoubles : kLdsDoubles;
+  __shared__ double lds[kLds];
+  __shared__ PassCtx<T> pctx;
+  __shared__ SmallState S;       // used by workgroup 0 only
+  __shared__ int s_phase;
+  set_vgrid((int)blockIdx.x, (int)gridDim.x);
+  unsigned epoch = 0;
+  solve_instance<Op, T>(*Pp, *opp, S, pctx, lds, s_phase, epoch);
+}
+
+// Groups of workgroups, each running the solves queued for it one after
+// another (batched and served forms).  Group g is workgroups
+// [g * group_size, (g+1) * group_size); its queue lists parameter blocks
+// (KParams, operator struct at +2048) that the host prepared for that group's
+// workspace.  A group waits for entry e until the host has published it
+// (queue tail > e) or has closed the queue; it reports entry e done by
+// storing e + 1 into `done`.  Waiting is bounded by the queue's idle limit.
+template <class Op, typename T>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Op::kWavesPerEU, 8)))
+kiops_group_kernel(GroupQueue* __restrict__ queues, int group_size) {
+  constexpr int kLds = Op::kLdsDoubles > kLdsDoubles ? Op::kLdsDoubles : kLdsDoubles;
+  __shared__ double lds[kLds];
+  __shared__ PassCtx<T> pctx;
+  __shared__ SmallState S;
+  __shared__ int s_phase;
+  __shared__ long long s_entry;
+  const int g = (int)blockIdx.x / group_size;
+  set_vgrid((int)blockIdx.x % group_size, group_size);
+  GroupQueue& Q = queues[g];
+  unsigned epoch = 0;
+  for (unsigned e = 0;; ++e) {
+    if (threadIdx.x == 0) {
+      long long found = -1;
+      const uint64_t t0 = (uint64_t)wall_clock64();
+      for (unsigned spins = 0;; ++spins) {
+        if (__hip_atomic_load(&Q.tail, __ATOMIC_ACQUIRE, KIOPS_AGENT) > e) { found = e; break; }
+        if (__hip_atomic_load(&Q.closed, __ATOMIC_RELAXED, KIOPS_AGENT)) break;
+        if ((uint64_t)wall_clock64() - t0 > Q.idle_limit) break;
+        __builtin_amdgcn_s_sleep(8);
+      }
+      s_entry = found;
+    }
+    __syncthreads();
+    const long long entry = s_entry;
+    __syncthreads();
+    if (entry < 0) return;
+    const unsigned char* blk = Q.blocks[entry % kGroupQueueLen];
+    const KParams& P = *reinterpret_cast<const KParams*>(blk);
+    const Op& op = *reinterpret_cast<const Op*>(blk + 2048);
+    solve_instance<Op, T>(P, op, S, pctx, lds, s_phase, epoch);
+    if (vblock() == 0 && threadIdx.x == 0) {
+      __threadfence();
+      __hip_atomic_store(&Q.done, e + 1, __ATOMIC_RELEASE, KIOPS_AGENT);
+    }
   }
 }
 

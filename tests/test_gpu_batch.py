@@ -1,0 +1,97 @@
+"""GPU parity of the batched form (many problems in one persistent launch).
+
+Each problem of a batch must match the oracle exactly as a single solve does
+(dense Theorem-1 result, relative 2-norm error <= 1e-8 at tol 1e-8, <= 1e-5
+for the mixed form at tol 1e-6), whatever the group size, and agree with the
+same problem solved alone.  Batches of 2-D (different sizes, p, tau and
+coefficients, as in the batched workload's recipe) and of 3-D problems are
+checked; operators of different families in one batch are refused.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import augmented, operators
+
+from gpu_helpers import announce, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(count, seed, precision="fp64", side_range=(16, 64)):
+    return W.cfg4(count=count, seed=seed, precision=precision, side_range=side_range)
+
+
+def _problems(prs, precision="fp64"):
+    import paper_1804_05126_amd as K
+    out = []
+    for pr in prs:
+        op = K.Operator.from_desc(pr.op, precision=precision)
+        out.append(dict(op=op, tau=pr.tau, vectors=to_dev(pr.vectors), tol=pr.tol, m_init=pr.m_init, q=pr.q))
+    return out
+
+
+@pytest.mark.parametrize("group_size", [0, 8, 16])
+def test_batch_2d_vs_dense(group_size):
+    import paper_1804_05126_amd as K
+    prs = _small_batch(12, seed=4001)
+    announce(f"batch of 12 2-D problems, group_size={group_size}")
+    ws, stats, status, plan = K.phi_batch(_problems(prs), group_size=group_size)
+    announce(f"  plan (groups, group size) = {plan}")
+    assert status == 0
+    for pr, w, st in zip(prs, ws, stats):
+        assert st["status"] == 0
+        ref = augmented.phi_combination_dense(operators.dense(pr.op), pr.tau, pr.vectors)
+        assert rel(w.cpu().numpy(), ref) <= 1e-8, (pr.name, st)
+
+
+def test_batch_matches_single_solves():
+    import paper_1804_05126_amd as K
+    prs = _small_batch(8, seed=4002, side_range=(40, 120))
+    probs = _problems(prs)
+    announce("batch of 8 vs the same problems solved alone")
+    ws, stats, status, plan = K.phi_batch(probs, group_size=8)
+    assert status == 0
+    for pr, pb, w in zip(prs, probs, ws):
+        single, st, _ = K.phi_combination(pb["op"], pr.tau, pb["vectors"], tol=pr.tol)
+        assert rel(w.cpu().numpy(), single.cpu().numpy()) <= 1e-8
+
+
+def test_batch_mixed_vs_dense():
+    import paper_1804_05126_amd as K
+    prs = _small_batch(8, seed=4003, precision="mixed")
+    announce("mixed batch of 8")
+    ws, stats, status, plan = K.phi_batch(_problems(prs, precision="mixed"), group_size=8)
+    assert status == 0
+    for pr, w in zip(prs, ws):
+        ref = augmented.phi_combination_dense(operators.dense(pr.op), pr.tau, pr.vectors)
+        assert rel(w.cpu().numpy(), ref) <= 1e-5
+
+
+def test_batch_3d_vs_dense():
+    import paper_1804_05126_amd as K
+    prs = [W.diffusion3d_problem(s, p, t, seed=4100 + s, tol=1e-8)
+           for s, p, t in ((8, 1, 2e-3), (12, 2, 1e-3), (16, 3, 5e-4), (10, 4, 1e-3))]
+    announce("batch of 4 3-D problems")
+    ws, stats, status, plan = K.phi_batch(_problems(prs), group_size=8)
+    assert status == 0
+    for pr, w in zip(prs, ws):
+        ref = augmented.phi_combination_dense(operators.dense(pr.op), pr.tau, pr.vectors)
+        assert rel(w.cpu().numpy(), ref) <= 1e-8
+
+
+def test_batch_refuses_mixed_families():
+    import paper_1804_05126_amd as K
+    prs = [_small_batch(1, seed=4004)[0], W.diffusion3d_problem(8, 1, 1e-3, seed=4005)]
+    announce("batch with a 2-D and a 3-D operator")
+    with pytest.raises(K.KiopsError):
+        K.phi_batch(_problems(prs))
+
+
+def test_batch_tune_picks_a_candidate():
+    import paper_1804_05126_amd as K
+    prs = _small_batch(16, seed=4006, side_range=(32, 96))
+    announce("autotune over group sizes 8, 16")
+    best, ms = K.batch_tune(_problems(prs), candidates=(8, 16))
+    assert best in (8, 16) and ms > 0
