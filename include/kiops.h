@@ -89,7 +89,7 @@ typedef struct {
 } kiops_operator_desc;
 
 /* Bounds of the Krylov dimension (Algorithm 1 inputs m_min, m_max; defaults
- * 10 and 128, Section 3.6.2; m_max defaults to 64 for KIOPS_MIXED operators,
+ * 10 and 128, Section 3.6.2; m_max defaults to 32 for KIOPS_MIXED operators,
  * whose FP32 basis loses accuracy over longer recurrences) and a cap on
  * substeps (default 100000).  A zero field takes its default.  m_max must not
  * exceed KIOPS_M_MAX_LIMIT. */
@@ -212,6 +212,46 @@ kiops_status kiops_phi_batch(int count, const kiops_problem* probs, const kiops_
 kiops_status kiops_batch_tune(int count, const kiops_problem* probs, const kiops_options* opts,
                               const int* candidates, int n, void* workspace, size_t workspace_bytes,
                               void* hip_stream, int* best, double* best_ms);
+
+/*
+ * Served form (continuous batching): one long-lived launch whose groups of
+ * workgroups each run one admitted request at a time.  Requests (2-D 5-point
+ * or 3-D 7-point stencil operators, FP64 or mixed, p <= 4, q in 1..4) are
+ * queued by kiops_server_submit and admitted, in arrival order, when a group
+ * is free and their workspace fits the memory pool (the HBM budget);
+ * kiops_server_progress retires finished requests and admits waiting ones.
+ * The launch uses one workgroup per CU, leaving the rest of the device to
+ * other work.  Memory: the caller's workspace holds the per-group state and
+ * the pool; the library allocates nothing.  Not thread-safe: one host thread
+ * drives a server.
+ */
+typedef struct kiops_server kiops_server;
+
+/* Bytes of the fixed part of a server workspace for groups of group_size
+ * workgroups (0 = 16), and the number of groups; the pool is what the caller
+ * adds on top. */
+kiops_status kiops_server_fixed_bytes(int group_size, size_t* bytes, int* groups);
+
+/* Launch the server on run_stream (hipStream_t); io_stream (another stream)
+ * carries the uploads and polls.  workspace: device, 256-byte aligned, at
+ * least the fixed bytes; the remainder is the request pool. */
+kiops_status kiops_server_create(int group_size, void* workspace, size_t workspace_bytes, void* run_stream,
+                                 void* io_stream, kiops_server** out);
+
+/* Queue a request; *ticket identifies it.  The problem's arrays must stay
+ * valid until the request is done.  BUDGET if it can never fit the pool. */
+kiops_status kiops_server_submit(kiops_server* s, const kiops_problem* pr, int64_t* ticket);
+
+/* Retire finished requests and admit waiting ones; *running and *waiting
+ * report the counts afterwards (either may be NULL). */
+kiops_status kiops_server_progress(kiops_server* s, int* running, int* waiting);
+
+/* *done = 1 once the request has finished; then *stats holds its statistics
+ * (stats->status is its status). */
+kiops_status kiops_server_result(kiops_server* s, int64_t ticket, int* done, kiops_stats* stats);
+
+/* Close the queues, wait for the launch to end and free the host object. */
+kiops_status kiops_server_destroy(kiops_server* s);
 
 /* Human-readable name of a status code (static storage). */
 const char* kiops_status_string(kiops_status s);

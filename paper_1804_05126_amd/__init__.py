@@ -17,7 +17,7 @@ from typing import List, Optional, Sequence
 from . import _lib
 from ._lib import KiopsError  # noqa: F401
 
-__all__ = ["Operator", "phi_combination", "phi_batch", "batch_tune", "iop_basis", "small_expm",
+__all__ = ["Operator", "phi_combination", "phi_batch", "batch_tune", "Server", "iop_basis", "small_expm",
            "controller_decide", "KiopsError"]
 
 
@@ -249,6 +249,75 @@ def batch_tune(problems: Sequence[dict], candidates=(8, 16, 32, 64), m_min: int 
                                     C.c_void_p(s.cuda_stream), C.byref(best), C.byref(best_ms)),
                "kiops_batch_tune")
     return best.value, best_ms.value
+
+
+class Server:
+    """Served form: a long-lived launch that runs admitted requests on groups of
+    workgroups (continuous batching).  pool_bytes is the HBM budget for the
+    requests' workspaces.  While a server is open, do not synchronise the whole
+    device (torch.cuda.synchronize) and do not run one-solve or batched launches:
+    both need every CU and would wait for the server."""
+
+    def __init__(self, pool_bytes: int, group_size: int = 16):
+        torch = _torch()
+        self._lib = lib = _lib.load()
+        fixed, groups = C.c_size_t(), C.c_int()
+        _lib.check(lib.kiops_server_fixed_bytes(int(group_size), C.byref(fixed), C.byref(groups)),
+                   "kiops_server_fixed_bytes")
+        self.groups = groups.value
+        total = fixed.value + int(pool_bytes)
+        self._ws = torch.empty(total + 256, dtype=torch.uint8, device="cuda")
+        base = _ptr(self._ws)
+        aligned = (base + 255) // 256 * 256
+        self.run_stream = torch.cuda.Stream()
+        self.io_stream = torch.cuda.Stream()
+        torch.cuda.current_stream().synchronize()
+        h = C.c_void_p()
+        _lib.check(lib.kiops_server_create(int(group_size), C.c_void_p(aligned), total,
+                                           C.c_void_p(self.run_stream.cuda_stream),
+                                           C.c_void_p(self.io_stream.cuda_stream), C.byref(h)),
+                   "kiops_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, op: Operator, tau: float, vectors: Sequence, tol: float = 1e-8, m_init: int = 10,
+               q: int = 2, out=None) -> int:
+        torch = _torch()
+        arr, keep, outs = _batch_problems([dict(op=op, tau=tau, vectors=vectors, tol=tol, m_init=m_init, q=q,
+                                                out=out)])
+        torch.cuda.current_stream().synchronize()     # inputs written on this stream are complete
+        t = C.c_int64()
+        _lib.check(self._lib.kiops_server_submit(self._h, arr, C.byref(t)), "kiops_server_submit")
+        self._keep[t.value] = (op, list(vectors), outs[0], keep)
+        return t.value
+
+    def progress(self):
+        r, w = C.c_int(), C.c_int()
+        _lib.check(self._lib.kiops_server_progress(self._h, C.byref(r), C.byref(w)), "kiops_server_progress")
+        return r.value, w.value
+
+    def result(self, ticket: int):
+        """(done, stats dict, w); after done the ticket is released."""
+        d = C.c_int()
+        st = _lib.Stats()
+        _lib.check(self._lib.kiops_server_result(self._h, int(ticket), C.byref(d), C.byref(st)),
+                   "kiops_server_result")
+        if not d.value:
+            return False, None, None
+        op, vectors, w, keep = self._keep.pop(ticket)
+        return True, st.as_dict(), w
+
+    def close(self):
+        if getattr(self, "_h", None):
+            status = self._lib.kiops_server_destroy(self._h)
+            self._h = None
+            _lib.check(status, "kiops_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def iop_basis(op: Operator, vectors: Sequence, m: int, q: int = 2):

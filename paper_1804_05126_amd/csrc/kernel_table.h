@@ -9,6 +9,7 @@ namespace kiops {
 const void* kernels_stencil2d(bool mixed, int pb, bool group);
 const void* kernels_stencil3d(bool mixed, int pb, bool group);
 const void* kernels_csr(bool mixed, int pb, bool group);
+const void* kernels_serve();   // served form: 2-D and 3-D stencils, FP64 and mixed, p <= 4
 
 #ifdef KIOPS_KERNEL_UNIT
 template <template <typename, int> class OP>

@@ -6,8 +6,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
+#include <deque>
+#include <map>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/kiops.h"
@@ -30,6 +34,8 @@ struct kiops_operator {
   void* ws;
   size_t ws_bytes;
 };
+
+struct kiops_server;
 
 namespace kiops {
 
@@ -157,12 +163,14 @@ kiops_status grid_size(const kiops_operator* op, int p, int* nwg) {
   return KIOPS_OK;
 }
 
-// Default m_max: 128 (Section 3.6.2); 64 for the mixed form, whose FP32 basis
-// loses accuracy over long recurrences (measured on the 256^3 and 2048^2
-// workloads: relative error 2.6e-4 at m = 128 against 6.7e-6 at m <= 64).
+// Default m_max: 128 (Section 3.6.2); 32 for the mixed form, whose FP32 basis
+// loses accuracy over long recurrences (measured relative errors at m_max 128 /
+// 64 / 32: 2.6e-4 / 6.7e-6 / 1.6e-6 on the 256^3 constant-coefficient box,
+// 1.8e-4 / 1.8e-4 / 9.9e-7 and 3.2e-5 / 3.2e-5 / 5.6e-6 on small 3-D boxes
+// with tau ||A||_1 of 306 and 101).
 void resolve_options(const kiops_operator* op, const kiops_options* o, int* m_min, int* m_max,
                      int* max_sub) {
-  const int m_default = op->d.precision == KIOPS_MIXED ? 64 : 128;
+  const int m_default = op->d.precision == KIOPS_MIXED ? 32 : 128;
   *m_min = (o && o->m_min > 0) ? o->m_min : 10;
   *m_max = (o && o->m_max > 0) ? o->m_max : m_default;
   *max_sub = (o && o->max_substeps > 0) ? o->max_substeps : 100000;
@@ -199,7 +207,16 @@ Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
   return L;
 }
 
-bool hip_ok(hipError_t e) { return e == hipSuccess; }
+// A failed HIP call; with KIOPS_DEBUG=1 in the environment it is reported on stderr.
+bool hip_ok(hipError_t e) {
+  if (e == hipSuccess) return true;
+  static const bool debug = [] {
+    const char* v = std::getenv("KIOPS_DEBUG");
+    return v && std::atoi(v) > 0;
+  }();
+  if (debug) std::fprintf(stderr, "kiops: HIP error %d: %s\n", (int)e, hipGetErrorString(e));
+  return false;
+}
 
 template <typename T, int PB>
 Stencil2D<T, PB> make_stencil2d(const kiops_operator* op, int p, const double* const* V, char* ws,
@@ -702,6 +719,140 @@ kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B
   return first;
 }
 
+// ---------------------------------------------------------------- server
+
+constexpr int kServePB = 4;   // p-bucket of the served kernel (p <= 4)
+
+int serve_family(const kiops_operator* op) {
+  const bool mixed = op->d.precision == KIOPS_MIXED;
+  if (op->d.kind == KIOPS_OP_CSR) return -1;
+  if (uses_3d(op)) return mixed ? kFamily3DMixed : kFamily3D;
+  return mixed ? kFamily2DMixed : kFamily2D;
+}
+
+// Per-group fixed state of a server: barrier words, arrival flags and clocks.
+size_t group_area_bytes(int gs) {
+  return align_up(sizeof(Barrier)) + align_up(sizeof(unsigned) * gs) + align_up(sizeof(uint64_t) * 3 * gs);
+}
+
+kiops_status serve_geometry(int group_size, int* gs_out, int* ng_out) {
+  int dev = 0, cus = 0;
+  if (!hip_ok(hipGetDevice(&dev)) ||
+      !hip_ok(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)))
+    return KIOPS_ERR_DEVICE;
+  const int gs = group_size > 0 ? group_size : 16;
+  if (gs > cus) return KIOPS_ERR_INVALID_ARG;
+  *gs_out = gs;
+  *ng_out = cus / gs;   // one workgroup per CU
+  return KIOPS_OK;
+}
+
+}  // namespace
+
+struct kiops_server {
+  struct Req {
+    kiops_problem pr;
+    std::vector<const double*> V;
+    int group = -1;
+    size_t pool_off = 0, pool_bytes = 0;
+    int done = 0;
+    Ctrl ctrl{};
+  };
+  hipStream_t run = nullptr, io = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int gs = 0, ng = 0;
+  uint64_t clock_hz = 0;
+  size_t area_off = 0, queue_off = 0, ctrl_off = 0, block_off = 0, pool_off = 0, pool_bytes = 0;
+  std::map<size_t, size_t> free_list;   // pool offset -> bytes
+  std::deque<int64_t> waiting;
+  std::unordered_map<int64_t, Req> reqs;
+  std::vector<int64_t> group_req;       // running ticket per group, -1 if free
+  std::vector<unsigned> pushed;         // entries pushed per group
+  int64_t next_ticket = 1;
+  bool dead = false;
+};
+
+namespace {
+
+bool pool_alloc(kiops_server* s, size_t bytes, size_t* off) {
+  for (auto it = s->free_list.begin(); it != s->free_list.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t at = it->first + bytes;
+      s->free_list.erase(it);
+      if (rest > 0) s->free_list[at] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void pool_free(kiops_server* s, size_t off, size_t bytes) {
+  auto it = s->free_list.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != s->free_list.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    s->free_list.erase(nx);
+  }
+  if (it != s->free_list.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      s->free_list.erase(it);
+    }
+  }
+}
+
+size_t request_bytes(const kiops_server* s, const kiops_problem& pr) {
+  int m_min, m_max, max_sub;
+  resolve_options(pr.op, nullptr, &m_min, &m_max, &max_sub);
+  return align_up(make_layout(pr.op, pr.p, pr.q, m_max, s->gs).total);
+}
+
+// Admit request t on free group g with pool block off.
+kiops_status admit(kiops_server* s, int64_t t, int g, size_t off) {
+  kiops_server::Req& R = s->reqs[t];
+  const kiops_problem& pr = R.pr;
+  int m_min, m_max, max_sub;
+  resolve_options(pr.op, nullptr, &m_min, &m_max, &max_sub);
+  char* base = s->ws + s->pool_off + off;
+  const Layout L = make_layout(pr.op, pr.p, pr.q, m_max, s->gs);
+  KParams P = make_params(pr.op, L, base, pr.tau, pr.p, R.V.data(), pr.tol, pr.m_init, pr.q, m_min, m_max,
+                          max_sub, kModeSolve, pr.w);
+  char* area = s->ws + s->area_off + group_area_bytes(s->gs) * g;
+  P.bar = reinterpret_cast<Barrier*>(area);
+  P.arrive = reinterpret_cast<unsigned*>(area + align_up(sizeof(Barrier)));
+  P.arrive_t = reinterpret_cast<uint64_t*>(area + align_up(sizeof(Barrier)) + align_up(sizeof(unsigned) * s->gs));
+  P.ctrl = reinterpret_cast<Ctrl*>(s->ws + s->ctrl_off + ctrl_stride() * g);
+  P.family = serve_family(pr.op);
+  alignas(256) unsigned char blk[4096];
+  std::memset(blk, 0, sizeof(blk));
+  std::memcpy(blk, &P, sizeof(KParams));
+  kiops_status st = stage_op_block(pr.op, pr.p, kServePB, R.V.data(), base, L, blk);
+  if (st != KIOPS_OK) return st;
+  Ctrl c{};
+  c.phase = kPhaseDone;
+  c.status = KIOPS_ERR_DEVICE;
+  unsigned char* dblk = reinterpret_cast<unsigned char*>(s->ws + s->block_off + (size_t)4096 * g);
+  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->queue_off) + g;
+  const unsigned e = s->pushed[g];
+  const unsigned char* ptr = dblk;
+  const unsigned tail = e + 1;
+  if (!hip_ok(hipMemcpyAsync(P.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s->io)) ||
+      !hip_ok(hipMemcpyAsync(dblk, blk, sizeof(blk), hipMemcpyHostToDevice, s->io)) ||
+      !hip_ok(hipMemcpyAsync(&dq->blocks[e % kGroupQueueLen], &ptr, sizeof(ptr), hipMemcpyHostToDevice, s->io)) ||
+      !hip_ok(hipMemcpyAsync(&dq->tail, &tail, sizeof(tail), hipMemcpyHostToDevice, s->io)) ||
+      !hip_ok(hipStreamSynchronize(s->io)))
+    return KIOPS_ERR_DEVICE;
+  s->pushed[g] = tail;
+  s->group_req[g] = t;
+  R.group = g;
+  R.pool_off = off;
+  return KIOPS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -932,6 +1083,169 @@ kiops_status kiops_batch_tune(int count, const kiops_problem* probs, const kiops
   *best = bgs;
   if (best_ms) *best_ms = bms;
   return KIOPS_OK;
+}
+
+kiops_status kiops_server_fixed_bytes(int group_size, size_t* bytes, int* groups) {
+  int gs = 0, ng = 0;
+  kiops_status st = serve_geometry(group_size, &gs, &ng);
+  if (st != KIOPS_OK) return st;
+  const size_t fixed = align_up(group_area_bytes(gs) * ng) + align_up(sizeof(GroupQueue) * ng) +
+                       align_up(ctrl_stride() * ng) + align_up((size_t)4096 * ng);
+  if (bytes) *bytes = fixed;
+  if (groups) *groups = ng;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_server_create(int group_size, void* workspace, size_t workspace_bytes, void* run_stream,
+                                 void* io_stream, kiops_server** out) {
+  if (!out || !workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return KIOPS_ERR_INVALID_ARG;
+  if (run_stream == io_stream) return KIOPS_ERR_INVALID_ARG;
+  int gs = 0, ng = 0;
+  kiops_status st = serve_geometry(group_size, &gs, &ng);
+  if (st != KIOPS_OK) return st;
+  size_t fixed = 0;
+  kiops_server_fixed_bytes(gs, &fixed, nullptr);
+  if (workspace_bytes <= fixed) return KIOPS_ERR_OUT_OF_MEMORY;
+  kiops_server* s = new (std::nothrow) kiops_server();
+  if (!s) return KIOPS_ERR_OUT_OF_MEMORY;
+  s->run = reinterpret_cast<hipStream_t>(run_stream);
+  s->io = reinterpret_cast<hipStream_t>(io_stream);
+  s->ws = reinterpret_cast<char*>(workspace);
+  s->ws_bytes = workspace_bytes;
+  s->gs = gs;
+  s->ng = ng;
+  int dev = 0, khz = 0;
+  hipGetDevice(&dev);
+  if (!hip_ok(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) || khz <= 0) khz = 100000;
+  s->clock_hz = (uint64_t)khz * 1000ull;
+  s->area_off = 0;
+  s->queue_off = align_up(group_area_bytes(gs) * ng);
+  s->ctrl_off = s->queue_off + align_up(sizeof(GroupQueue) * ng);
+  s->block_off = s->ctrl_off + align_up(ctrl_stride() * ng);
+  s->pool_off = s->block_off + align_up((size_t)4096 * ng);
+  s->pool_bytes = (workspace_bytes - s->pool_off) / kAlign * kAlign;
+  s->free_list[0] = s->pool_bytes;
+  s->group_req.assign(ng, -1);
+  s->pushed.assign(ng, 0);
+  std::vector<GroupQueue> q(ng);
+  for (auto& Q : q) {
+    std::memset(&Q, 0, sizeof(GroupQueue));
+    Q.idle_limit = s->clock_hz * 600ull;   // a launch nobody feeds ends after ten minutes
+  }
+  if (!hip_ok(hipMemsetAsync(s->ws + s->area_off, 0, s->queue_off - s->area_off, s->io)) ||
+      !hip_ok(hipMemcpyAsync(s->ws + s->queue_off, q.data(), sizeof(GroupQueue) * ng, hipMemcpyHostToDevice, s->io)) ||
+      !hip_ok(hipStreamSynchronize(s->io))) {
+    delete s;
+    return KIOPS_ERR_DEVICE;
+  }
+  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->queue_off);
+  void* args[] = {&dq, &s->gs};
+  if (!hip_ok(hipLaunchCooperativeKernel(kernels_serve(), dim3(ng * gs), dim3(kThreads), args, 0, s->run))) {
+    delete s;
+    return KIOPS_ERR_DEVICE;
+  }
+  *out = s;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_server_submit(kiops_server* s, const kiops_problem* pr, int64_t* ticket) {
+  if (!s || !pr || !ticket) return KIOPS_ERR_INVALID_ARG;
+  if (s->dead) return KIOPS_ERR_DEVICE;
+  if (!pr->op || !(pr->tau >= 0.0) || !std::isfinite(pr->tau) || !(pr->tol > 0.0) || !std::isfinite(pr->tol) ||
+      pr->m_init < 1 || pr->q < 1 || pr->q > kWinMax || pr->p < 0 || pr->p > kServePB)
+    return pr->q == 0 ? KIOPS_ERR_UNSUPPORTED : KIOPS_ERR_INVALID_ARG;
+  kiops_status st = check_vectors(pr->op, pr->p, pr->V, pr->w);
+  if (st != KIOPS_OK) return st;
+  if (serve_family(pr->op) < 0) return KIOPS_ERR_UNSUPPORTED;
+  if (request_bytes(s, *pr) > s->pool_bytes) return KIOPS_ERR_BUDGET;
+  kiops_server::Req R;
+  R.pr = *pr;
+  R.V.assign(pr->V, pr->V + pr->p + 1);
+  R.pr.V = nullptr;
+  const int64_t t = s->next_ticket++;
+  s->reqs.emplace(t, std::move(R));
+  s->waiting.push_back(t);
+  *ticket = t;
+  return kiops_server_progress(s, nullptr, nullptr);
+}
+
+kiops_status kiops_server_progress(kiops_server* s, int* running, int* waiting) {
+  if (!s) return KIOPS_ERR_INVALID_ARG;
+  if (s->dead) return KIOPS_ERR_DEVICE;
+  // the done and exited words of every group queue
+  std::vector<unsigned> words(2 * s->ng, 0);
+  const GroupQueue* dq = reinterpret_cast<const GroupQueue*>(s->ws + s->queue_off);
+  if (!hip_ok(hipMemcpy2DAsync(words.data(), 2 * sizeof(unsigned), &dq->done, sizeof(GroupQueue),
+                               2 * sizeof(unsigned), s->ng, hipMemcpyDeviceToHost, s->io)) ||
+      !hip_ok(hipStreamSynchronize(s->io)))
+    return KIOPS_ERR_DEVICE;
+  {
+    for (int g = 0; g < s->ng; ++g) {
+      if (words[2 * g + 1]) {   // a group has left: its launch is over
+        if (std::getenv("KIOPS_DEBUG")) std::fprintf(stderr, "kiops: server group %d has exited\n", g);
+        s->dead = true;
+        return KIOPS_ERR_DEVICE;
+      }
+      const int64_t t = s->group_req[g];
+      if (t < 0 || words[2 * g] < s->pushed[g]) continue;
+      kiops_server::Req& R = s->reqs[t];
+      if (!hip_ok(hipMemcpyAsync(&R.ctrl, s->ws + s->ctrl_off + ctrl_stride() * g, sizeof(Ctrl),
+                                 hipMemcpyDeviceToHost, s->io)) ||
+          !hip_ok(hipStreamSynchronize(s->io)))
+        return KIOPS_ERR_DEVICE;
+      R.done = 1;
+      pool_free(s, R.pool_off, request_bytes(s, R.pr));
+      s->group_req[g] = -1;
+    }
+  }
+  // admit waiting requests in arrival order (a request that does not fit the
+  // pool yet lets at most eight later ones go first)
+  for (size_t k = 0; k < s->waiting.size() && k < 9;) {
+    int g = -1;
+    for (int h = 0; h < s->ng; ++h)
+      if (s->group_req[h] < 0) { g = h; break; }
+    if (g < 0) break;
+    const int64_t t = s->waiting[k];
+    size_t off = 0;
+    if (!pool_alloc(s, request_bytes(s, s->reqs[t].pr), &off)) { ++k; continue; }
+    kiops_status st = admit(s, t, g, off);
+    if (st != KIOPS_OK) return st;
+    s->waiting.erase(s->waiting.begin() + k);
+  }
+  if (running) {
+    int r = 0;
+    for (int g = 0; g < s->ng; ++g) r += s->group_req[g] >= 0;
+    *running = r;
+  }
+  if (waiting) *waiting = (int)s->waiting.size();
+  return KIOPS_OK;
+}
+
+kiops_status kiops_server_result(kiops_server* s, int64_t ticket, int* done, kiops_stats* stats) {
+  if (!s || !done) return KIOPS_ERR_INVALID_ARG;
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return KIOPS_ERR_INVALID_ARG;
+  *done = it->second.done;
+  if (it->second.done) {
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      fill_stats(it->second.ctrl, s->gs, (double)s->clock_hz, stats);
+    }
+    s->reqs.erase(it);
+  }
+  return KIOPS_OK;
+}
+
+kiops_status kiops_server_destroy(kiops_server* s) {
+  if (!s) return KIOPS_ERR_INVALID_ARG;
+  const unsigned one = 1;
+  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->queue_off);
+  kiops_status st = KIOPS_OK;
+  for (int g = 0; g < s->ng; ++g)
+    if (!hip_ok(hipMemcpyAsync(&dq[g].closed, &one, sizeof(one), hipMemcpyHostToDevice, s->io))) st = KIOPS_ERR_DEVICE;
+  if (!hip_ok(hipStreamSynchronize(s->io)) || !hip_ok(hipStreamSynchronize(s->run))) st = KIOPS_ERR_DEVICE;
+  delete s;
+  return st;
 }
 
 kiops_status kiops_controller_decide(const kiops_ctrl_in* in, int j, double eps, int breakdown,

@@ -27,6 +27,8 @@ constexpr int kXcds = 8;                            // accelerator complex dies 
 enum Phase : int32_t { kPhasePass = 0, kPhaseGather = 1, kPhaseDone = 2, kPhaseDots = 3 };
 constexpr int kDotFullStride = 2 * kLdh;            // full-window inner products per workgroup
 enum Mode : int32_t { kModeSolve = 0, kModeBasis = 1 };
+// Served form: which solver body a request runs (p <= 4).
+enum Family : int32_t { kFamily2D = 0, kFamily2DMixed = 1, kFamily3D = 2, kFamily3DMixed = 3 };
 
 // The solve a workgroup works on: its index among that solve's workgroups and
 // their number (the whole grid for a single solve; one group of workgroups of
@@ -92,6 +94,7 @@ struct KParams {
   int p, q, m_min, m_max, m_init, max_substeps;
   int mode, mixed, nwg, ndot_stride;
   int profile;                 // record per-workgroup arrival times (diagnostics)
+  int family;                  // served form: operator family of the request (kFamily*)
   double T_end, tol;
   double elem_bytes;           // bytes per basis element (8 or 4)
   double coef_streams;         // per-cell coefficient arrays the operator reads
@@ -127,9 +130,11 @@ struct GroupQueue {
   unsigned tail;            // entries published (host)
   unsigned closed;          // no more entries will come (host)
   unsigned done;            // entries finished (device)
-  unsigned pad0;
+  unsigned exited;          // the group has left its loop (device)
   uint64_t idle_limit;      // wall-clock ticks a group waits for an entry
-  uint64_t pad1[13];        // one 128-byte line for the words above
+  unsigned exit_reason;     // why the group left: 1 closed, 2 idle (device)
+  unsigned exit_entry;      // the entry it was waiting for then (device)
+  uint64_t pad1[12];        // one 128-byte line for the words above
   const unsigned char* blocks[kGroupQueueLen];
 };
 

@@ -795,6 +795,33 @@ __device__ inline void dots_phase(const KParams& P, const BasisPtrs<T>& bp, doub
   __syncthreads();
 }
 
+// Entry e of a group queue: e once the host has published it, or -1 when the
+// queue is closed (and drained) or nothing came within its idle limit.  Called
+// by the whole first wave with wave-uniform values (one loop exit, one result).
+__device__ inline long long wait_entry(GroupQueue& Q, unsigned e) {
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  long long result = -2;
+  while (result == -2) {
+    const unsigned tail = __builtin_amdgcn_readfirstlane(__hip_atomic_load(&Q.tail, __ATOMIC_ACQUIRE, KIOPS_AGENT));
+    const unsigned closed =
+        __builtin_amdgcn_readfirstlane(__hip_atomic_load(&Q.closed, __ATOMIC_RELAXED, KIOPS_AGENT));
+    const bool idle = (uint64_t)wall_clock64() - t0 > Q.idle_limit;
+    if (tail > e) {
+      result = e;
+    } else if (closed || idle) {
+      if (threadIdx.x == 0) {
+        __hip_atomic_store(&Q.exit_reason, closed ? 1u : 2u, __ATOMIC_RELAXED, KIOPS_AGENT);
+        __hip_atomic_store(&Q.exit_entry, e, __ATOMIC_RELAXED, KIOPS_AGENT);
+      }
+      result = -1;
+    } else {
+      __builtin_amdgcn_s_sleep(8);
+    }
+  }
+  if (result >= 0) __threadfence();
+  return result;
+}
+
 // One solve (Algorithm 1) on the workgroups of the current virtual grid.
 // `epoch` is the grid-barrier epoch of this group of workgroups; it keeps
 // counting across the solves a group runs one after another.
@@ -885,21 +912,17 @@ kiops_group_kernel(GroupQueue* __restrict__ queues, int group_size) {
   GroupQueue& Q = queues[g];
   unsigned epoch = 0;
   for (unsigned e = 0;; ++e) {
-    if (threadIdx.x == 0) {
-      long long found = -1;
-      const uint64_t t0 = (uint64_t)wall_clock64();
-      for (unsigned spins = 0;; ++spins) {
-        if (__hip_atomic_load(&Q.tail, __ATOMIC_ACQUIRE, KIOPS_AGENT) > e) { found = e; break; }
-        if (__hip_atomic_load(&Q.closed, __ATOMIC_RELAXED, KIOPS_AGENT)) break;
-        if ((uint64_t)wall_clock64() - t0 > Q.idle_limit) break;
-        __builtin_amdgcn_s_sleep(8);
-      }
-      s_entry = found;
+    if (threadIdx.x < 64) {
+      const long long r = wait_entry(Q, e);
+      if (threadIdx.x == 0) s_entry = r;
     }
     __syncthreads();
     const long long entry = s_entry;
     __syncthreads();
-    if (entry < 0) return;
+    if (entry < 0) {
+      if (vblock() == 0 && threadIdx.x == 0) __hip_atomic_store(&Q.exited, 1u, __ATOMIC_RELEASE, KIOPS_AGENT);
+      return;
+    }
     const unsigned char* blk = Q.blocks[entry % kGroupQueueLen];
     const KParams& P = *reinterpret_cast<const KParams*>(blk);
     const Op& op = *reinterpret_cast<const Op*>(blk + 2048);
