@@ -42,10 +42,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-substeps", type=int, default=2)
     ap.add_argument("--traffic-json", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--workload", choices=("adr2d", "diff3d", "batch"), default="adr2d",
+    ap.add_argument("--workload", choices=("adr2d", "diff3d", "batch", "serve"), default="adr2d",
                     help="adr2d: the 2048^2 tau sweep (default); diff3d: the 256^3 variable-"
                          "coefficient solve; batch: 256 2-D problems in one launch vs a per-solve loop")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--serve-count", type=int, default=48, help="requests per arrival rate (serve)")
+    ap.add_argument("--serve-lams", type=str, default="100,1000,5000", help="arrival rates, req/s (serve)")
+    ap.add_argument("--serve-group", type=int, default=16, help="workgroups per server group (serve)")
+    ap.add_argument("--serve-pool-gb", type=float, default=64.0, help="HBM budget of the server (serve)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run one plain device copy of MIB MiB (a known-size "
                          "kernel that HBM traffic counters are scaled by)")
@@ -100,6 +104,8 @@ def main():
         return bench_diff3d(args, W, K, np, torch)
     if args.workload == "batch":
         return bench_batch(args, W, K, np, torch)
+    if args.workload == "serve":
+        return bench_serve(args, W, K, np, torch)
     taus = [float(t) for t in args.taus.split(",")] if args.taus else W.cfg2_tau_grid()
     side = args.side
     pr = W.cfg2(side, taus[0], q=args.q)       # operator and vectors shared by the sweep
@@ -307,6 +313,131 @@ def bench_batch(args, W, K, np, torch):
         "batch_latency_ms": wall * 1e3 / args.steps,
         "autotune": {"candidates": [8, 16, 32, 64], "best_group_size": best, "best_ms": tune_ms},
         "statuses_ok": all(st["status"] == 0 for st in stats),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, W, K, np, torch):
+    """The served workload: a Poisson stream of requests (half 2-D ADR with side
+    log-U[64,2048], half 3-D diffusion-reaction with side log-U[32,192]; p in 1..4;
+    tau log-U[1e-4,1e-1]; half mixed at tol 1e-6, half FP64 at tol 1e-8) replayed
+    in real time at each arrival rate, against a server with an HBM budget.  The
+    same requests are also solved by the plain form, one at a time in arrival
+    order on the whole GPU (FIFO), replayed at the same arrival times.  Latency is
+    completion (as seen by the host loop) minus scheduled arrival."""
+    lams = [float(x) for x in args.serve_lams.split(",")]
+    reqs = W.cfg5_requests(lam=lams[0], count=args.serve_count)
+    gaps = np.diff([0.0] + [r.arrival_s for r in reqs]) * lams[0]   # unit-rate gaps; same draws at every rate
+    inputs = []
+    for r in reqs:
+        pr = r.materialize()
+        op = K.Operator.from_desc(pr.op, precision=pr.precision)
+        vecs = [torch.as_tensor(v, device="cuda") for v in pr.vectors]
+        w = torch.empty(pr.n, dtype=torch.float64, device="cuda")
+        inputs.append((r, op, vecs, w))
+        del pr
+    torch.cuda.synchronize()
+    print(f"[bench] {len(inputs)} requests ready", file=sys.stderr, flush=True)
+
+    def solve_alone(r, op, vecs, w):
+        _, st, status = K.phi_combination(op, r.tau, vecs, tol=r.tol, out=w)
+        return st
+    # warm-up: one small request of each family through the plain form
+    for r, op, vecs, w in sorted(inputs, key=lambda x: x[0].n)[:4]:
+        solve_alone(r, op, vecs, w)
+    torch.cuda.synchronize()
+    # service times of the plain form (each request alone on the whole GPU)
+    service = []
+    alg = 0.0
+    for r, op, vecs, w in inputs:
+        s0 = time.perf_counter()
+        st = solve_alone(r, op, vecs, w)
+        service.append(time.perf_counter() - s0)
+        alg += st["alg_bytes"]
+        print(f"[bench]   {r.kind} side {r.side} p {r.p} tau {r.tau:.2e} {r.precision}: "
+              f"{service[-1] * 1e3:.1f} ms, {st['matvecs']} matvecs", file=sys.stderr, flush=True)
+    print(f"[bench] plain-form service times measured: total {sum(service):.2f} s", file=sys.stderr, flush=True)
+
+    def fifo(arrivals):
+        """Plain form replayed live: each request starts when it has arrived and
+        the previous one has finished."""
+        lat = []
+        t0 = time.perf_counter()
+        for (r, op, vecs, w), a in zip(inputs, arrivals):
+            now = time.perf_counter() - t0
+            if now < a:
+                time.sleep(a - now)
+            solve_alone(r, op, vecs, w)
+            lat.append(time.perf_counter() - t0 - a)
+        return lat, time.perf_counter() - t0 - arrivals[0]
+
+    def served(arrivals):
+        srv = K.Server(pool_bytes=int(args.serve_pool_gb * (1 << 30)), group_size=args.serve_group)
+        lat = [None] * len(inputs)
+        tickets = {}
+        nxt = 0
+        stats = []
+        t0 = time.perf_counter()
+        try:
+            while len(stats) < len(inputs):
+                now = time.perf_counter() - t0
+                while nxt < len(inputs) and arrivals[nxt] <= now:
+                    r, op, vecs, w = inputs[nxt]
+                    tickets[srv.submit(op, r.tau, vecs, tol=r.tol, out=w)] = nxt
+                    nxt += 1
+                srv.progress()
+                finished = False
+                for t in list(tickets):
+                    done, st, _ = srv.result(t)
+                    if done:
+                        i = tickets.pop(t)
+                        lat[i] = time.perf_counter() - t0 - arrivals[i]
+                        stats.append(st)
+                        finished = True
+                        r = inputs[i][0]
+                        mv = max(st["matvecs"], 1)
+                        print(f"[bench]   served {r.kind} {r.side} {r.precision}: at {arrivals[i] * 1e3:.1f} ms, "
+                              f"latency {lat[i] * 1e3:.1f} ms, {st['grid_blocks']} wg, {mv} matvecs, per matvec "
+                              f"work {st['time_work_s'] / mv * 1e6:.1f} wait {st['time_wait_s'] / mv * 1e6:.1f} "
+                              f"epi {st['time_epilogue_s'] / mv * 1e6:.1f} us", file=sys.stderr, flush=True)
+                if not finished:
+                    time.sleep(2e-4)
+                if time.perf_counter() - t0 > 600:
+                    raise RuntimeError("served requests did not finish within 600 s")
+            span = time.perf_counter() - t0 - arrivals[0]
+        finally:
+            srv.close()
+        return lat, span, stats
+
+    rows = []
+    for lam in lams:
+        arrivals = list(np.cumsum(gaps) / lam)
+        lat_s, span_s, stats = served(arrivals)
+        ok = all(st["status"] == 0 for st in stats)
+        lat_f, span_f = fifo(arrivals)
+        row = {"lambda_req_s": lam,
+               "served": {"solves_per_s": len(inputs) / span_s, **_lat([x * 1e3 for x in lat_s]),
+                          "statuses_ok": ok},
+               "plain_fifo": {"solves_per_s": len(inputs) / span_f, **_lat([x * 1e3 for x in lat_f])}}
+        rows.append(row)
+        print(f"[bench] lambda {lam:g}: {json.dumps(row)}", file=sys.stderr, flush=True)
+    head = rows[min(1, len(rows) - 1)]
+    span = len(inputs) / head["served"]["solves_per_s"]
+    out = {
+        "metric": METRIC, "value": head["served"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": len(inputs), "warmup": 4, "ms_per_step": span * 1e3 / len(inputs), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 and f32-basis/f64-accumulate", "data": "synthetic",
+        "config": {"workload": (f"served: {len(inputs)} Poisson arrivals, 2-D ADR side log-U[64,2048] / "
+                                f"3-D diffusion-reaction side log-U[32,192], p~U{{1..4}}, tau~log-U[1e-4,1e-1], "
+                                f"tol 1e-6 mixed / 1e-8 FP64, HBM budget {args.serve_pool_gb:g} GB"),
+                   "lambda_req_s": head["lambda_req_s"], "group_size": args.serve_group,
+                   "requests_2d": sum(r.kind == "2d" for r, *_ in inputs),
+                   "requests_mixed": sum(r.precision == "mixed" for r, *_ in inputs)},
+        "roofline": {"bound": "hbm", "achieved": alg / span / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": alg / span / 1e9 / HBM_PEAK_GBS, "traffic": None, "kernel": "kiops_serve_kernel"},
+        "latency_ms": {k: head["served"][k] for k in ("p50", "p99")},
+        "sweep": rows,
+        "plain_service_s": {"total": sum(service), "max": max(service)},
     }
     print(json.dumps(out), flush=True)
 

@@ -214,29 +214,39 @@ kiops_status kiops_batch_tune(int count, const kiops_problem* probs, const kiops
                               void* hip_stream, int* best, double* best_ms);
 
 /*
- * Served form (continuous batching): one long-lived launch whose groups of
- * workgroups each run one admitted request at a time.  Requests (2-D 5-point
- * or 3-D 7-point stencil operators, FP64 or mixed, p <= 4, q in 1..4) are
- * queued by kiops_server_submit and admitted, in arrival order, when a group
- * is free and their workspace fits the memory pool (the HBM budget);
- * kiops_server_progress retires finished requests and admits waiting ones.
- * The launch uses one workgroup per CU, leaving the rest of the device to
- * other work.  Memory: the caller's workspace holds the per-group state and
- * the pool; the library allocates nothing.  Not thread-safe: one host thread
- * drives a server.
+ * Served form (continuous batching): one long-lived launch whose workgroups
+ * are split into groups of group_size; each admitted request runs on a gang,
+ * an aligned run of 2^j groups sized so that each workgroup gets at most
+ * points_per_workgroup grid points (capped at the largest power of two of
+ * groups the launch holds).  Requests (2-D 5-point or 3-D 7-point stencil
+ * operators, FP64 or mixed, p <= 4, q in 1..4) are queued by
+ * kiops_server_submit and admitted in arrival order when a gang is free and
+ * their workspace fits the memory pool (the HBM budget); when the oldest
+ * waiting request finds no free gang, the gang with the fewest busy groups is
+ * reserved for it and at most eight later requests may start elsewhere in the
+ * meantime.  kiops_server_progress retires finished requests and admits
+ * waiting ones.  The launch holds two workgroups per CU when the kernel fits
+ * three times on a CU (else one), so the device keeps room for the copies and
+ * small kernels of other streams.  Memory: the caller's workspace holds the
+ * per-group state and the pool; the library allocates nothing.  Not
+ * thread-safe: one host thread drives a server.  A bounded wait that expires
+ * inside the launch (a minute without progress) fails the request with
+ * KIOPS_ERR_DEVICE and the server with it: every later call returns
+ * KIOPS_ERR_DEVICE.
  */
 typedef struct kiops_server kiops_server;
 
 /* Bytes of the fixed part of a server workspace for groups of group_size
- * workgroups (0 = 16), and the number of groups; the pool is what the caller
- * adds on top. */
+ * workgroups (0 = 16; a multiple of 8), and the number of groups; the pool is
+ * what the caller adds on top. */
 kiops_status kiops_server_fixed_bytes(int group_size, size_t* bytes, int* groups);
 
 /* Launch the server on run_stream (hipStream_t); io_stream (another stream)
- * carries the uploads and polls.  workspace: device, 256-byte aligned, at
- * least the fixed bytes; the remainder is the request pool. */
-kiops_status kiops_server_create(int group_size, void* workspace, size_t workspace_bytes, void* run_stream,
-                                 void* io_stream, kiops_server** out);
+ * carries the uploads and polls.  points_per_workgroup: gang sizing (0 =
+ * 8192).  workspace: device, 256-byte aligned, at least the fixed bytes; the
+ * remainder is the request pool. */
+kiops_status kiops_server_create(int group_size, int64_t points_per_workgroup, void* workspace,
+                                 size_t workspace_bytes, void* run_stream, void* io_stream, kiops_server** out);
 
 /* Queue a request; *ticket identifies it.  The problem's arrays must stay
  * valid until the request is done.  BUDGET if it can never fit the pool. */

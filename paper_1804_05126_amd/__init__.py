@@ -252,13 +252,15 @@ def batch_tune(problems: Sequence[dict], candidates=(8, 16, 32, 64), m_min: int 
 
 
 class Server:
-    """Served form: a long-lived launch that runs admitted requests on groups of
-    workgroups (continuous batching).  pool_bytes is the HBM budget for the
-    requests' workspaces.  While a server is open, do not synchronise the whole
-    device (torch.cuda.synchronize) and do not run one-solve or batched launches:
-    both need every CU and would wait for the server."""
+    """Served form: a long-lived launch that runs admitted requests on gangs of
+    groups of workgroups (continuous batching).  pool_bytes is the HBM budget
+    for the requests' workspaces; a request gets the smallest power-of-two gang
+    of groups giving each workgroup at most points_per_workgroup grid points.
+    While a server is open, do not synchronise the whole device
+    (torch.cuda.synchronize) and do not run one-solve or batched launches: both
+    need every CU and would wait for the server."""
 
-    def __init__(self, pool_bytes: int, group_size: int = 16):
+    def __init__(self, pool_bytes: int, group_size: int = 16, points_per_workgroup: int = 0):
         torch = _torch()
         self._lib = lib = _lib.load()
         fixed, groups = C.c_size_t(), C.c_int()
@@ -273,7 +275,7 @@ class Server:
         self.io_stream = torch.cuda.Stream()
         torch.cuda.current_stream().synchronize()
         h = C.c_void_p()
-        _lib.check(lib.kiops_server_create(int(group_size), C.c_void_p(aligned), total,
+        _lib.check(lib.kiops_server_create(int(group_size), int(points_per_workgroup), C.c_void_p(aligned), total,
                                            C.c_void_p(self.run_stream.cuda_stream),
                                            C.c_void_p(self.io_stream.cuda_stream), C.byref(h)),
                    "kiops_server_create")

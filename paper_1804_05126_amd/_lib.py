@@ -122,7 +122,7 @@ SIGNATURES = [
                                    C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_int),
                                    C.POINTER(C.c_double)]),
     ("kiops_server_fixed_bytes", C.c_int, [C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_int)]),
-    ("kiops_server_create", C.c_int, [C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+    ("kiops_server_create", C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_void_p)]),
     ("kiops_server_submit", C.c_int, [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_int64)]),
     ("kiops_server_progress", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),

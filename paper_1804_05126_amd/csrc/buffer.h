@@ -14,9 +14,18 @@ namespace kiops {
 
 constexpr uint32_t kNoOffset = 0xFFFFFFF0u;
 
+// Every array a resource is made for is the same for the whole wave; the base
+// and extent are read from the first active lane so that the resource sits in
+// scalar registers even where the compiler cannot prove the pointer uniform
+// (a parameter block read from memory), which would otherwise wrap each
+// access in a loop over the distinct values of the lanes.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint64_t bytes) {
-  const int n = (p && bytes < 0xFFFFFFFFull) ? (int)(uint32_t)bytes : 0;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, n, 0x00020000);
+  const uint64_t b = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  const int n = __builtin_amdgcn_readfirstlane((p && bytes < 0xFFFFFFFFull) ? (int)(uint32_t)bytes : 0);
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0, n,
+                                           0x00020000);
 }
 __device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
@@ -54,6 +63,22 @@ __device__ __forceinline__ T* uniform(T* p) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
   return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+// Copy of a small trivially-copyable struct that is the same for the whole
+// wave, read word by word from memory and converted to wave-uniform values:
+// its fields can then live in scalar registers even though the memory it
+// came from may change later in the launch (so scalar loads are not allowed).
+template <class S>
+__device__ __forceinline__ S load_uniform(const S* src) {
+  static_assert(sizeof(S) % 4 == 0, "word-sized struct");
+  S out;
+  const uint32_t* from = reinterpret_cast<const uint32_t*>(src);
+  uint32_t words[sizeof(S) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) words[i] = __builtin_amdgcn_readfirstlane(from[i]);
+  __builtin_memcpy(&out, words, sizeof(S));
+  return out;
 }
 
 }  // namespace kiops

@@ -1,8 +1,8 @@
 // Served form: one long-lived launch whose groups of workgroups take solves
-// from their own queues as the host admits them.  A request may be a 2-D
-// 5-point or a 3-D 7-point problem in FP64 or mixed precision (p <= 4); the
-// parameter block says which (KParams::family) and the group runs the matching
-// solver body.
+// from their own queues as the host admits them; a large request runs on a
+// gang of several groups.  A request may be a 2-D 5-point or a 3-D 7-point
+// problem in FP64 or mixed precision (p <= 4); the parameter block says which
+// (KParams::family) and the group runs the matching solver body.
 #define KIOPS_KERNEL_UNIT
 #include "op_stencil2d.h"
 #include "op_stencil3d.h"
@@ -17,18 +17,62 @@ constexpr int kServeLds = cmax(cmax(Stencil3D<double, 4>::kLdsDoubles, Stencil2D
                                kLdsDoubles);
 }  // namespace
 
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
-kiops_serve_kernel(GroupQueue* __restrict__ queues, int group_size) {
-  __shared__ double lds[kServeLds];
-  __shared__ PassCtx<double> pd;
-  __shared__ PassCtx<float> pf;
-  __shared__ SmallState S;
-  __shared__ int s_phase;
+__shared__ double serve_lds[kServeLds];
+__shared__ PassCtx<double> serve_pd;
+__shared__ PassCtx<float> serve_pf;
+__shared__ SmallState serve_S;
+__shared__ int serve_phase;
+
+// The parameter block and operator struct are read-only for the whole solve
+// (restrict, kept through inlining), so their fields can stay in scalar
+// registers.
+template <class Op, typename T>
+__device__ __forceinline__ unsigned serve_body(const KParams* __restrict__ Pp, const Op* __restrict__ opp,
+                                               unsigned epoch) {
+  PassCtx<T>* pctx;
+  if constexpr (sizeof(T) == 8) pctx = &serve_pd;
+  else pctx = &serve_pf;
+  const Op op = load_uniform(opp);   // operator fields in scalar registers for the passes
+  solve_instance<Op, T>(*Pp, op, serve_S, *pctx, serve_lds, serve_phase, epoch);
+  return epoch;
+}
+
+// Wave-uniform bounded wait until every slot of fin[0..n) holds at least val.
+__device__ inline void wait_all_at_least(const unsigned* fin, int n, unsigned val, uint64_t limit) {
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  bool all = false;
+  while (!all) {
+    int ok = 1;
+    for (int j = (int)threadIdx.x; j < n; j += 64)
+      ok &= __hip_atomic_load(&fin[j], __ATOMIC_RELAXED, KIOPS_AGENT) >= val ? 1 : 0;
+    all = __all(ok) != 0;
+    const bool late = __builtin_amdgcn_readfirstlane((uint64_t)wall_clock64() - t0 > limit ? 1 : 0) != 0;
+    if (!all) {
+      if (late) break;
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __threadfence();
+}
+
+// Workgroup blockIdx.x belongs to group blockIdx.x / group_size and takes its
+// entries from that group's queue.  A request runs on a gang: the aligned run
+// of groups the host chose for it, whose workgroups [P.wg0, P.wg0 + P.nwg)
+// form the virtual grid of the solve (the host pushes the same parameter
+// block to every group of the gang).  Barrier slots are per workgroup
+// (arrive[blockIdx.x]) and the epoch starts from P.epoch0, which the host
+// sets to the largest epoch any workgroup of the gang has reached, so every
+// slot is below the epochs the solve will use.  A group reports an entry
+// done only after all of its workgroups have left the solve (fin), so the
+// host never reuses a parameter block, control block or workspace that a
+// workgroup may still read.
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 8)))
+kiops_serve_kernel(GroupQueue* __restrict__ queues, unsigned* __restrict__ fin, int group_size,
+                   uint64_t fin_limit) {
   __shared__ long long s_entry;
   const int g = (int)blockIdx.x / group_size;
-  set_vgrid((int)blockIdx.x % group_size, group_size);
+  const int local = (int)blockIdx.x % group_size;
   GroupQueue& Q = queues[g];
-  unsigned epoch = 0;
   for (unsigned e = 0;; ++e) {
     if (threadIdx.x < 64) {
       const long long r = wait_entry(Q, e);
@@ -38,33 +82,38 @@ kiops_serve_kernel(GroupQueue* __restrict__ queues, int group_size) {
     const long long entry = s_entry;
     __syncthreads();
     if (entry < 0) {
-      if (vblock() == 0 && threadIdx.x == 0) __hip_atomic_store(&Q.exited, 1u, __ATOMIC_RELEASE, KIOPS_AGENT);
+      if (local == 0 && threadIdx.x == 0) __hip_atomic_store(&Q.exited, 1u, __ATOMIC_RELEASE, KIOPS_AGENT);
       return;
     }
-    const unsigned char* blk = Q.blocks[entry % kGroupQueueLen];
+    // wave-uniform block pointer: the block's fields go to scalar registers
+    const unsigned char* blk = uniform(Q.blocks[uniform((int)(entry % kGroupQueueLen))]);
     const KParams& P = *reinterpret_cast<const KParams*>(blk);
     const void* op = blk + 2048;
+    set_vgrid((int)blockIdx.x - P.wg0, P.nwg);
+    unsigned epoch = P.epoch0;
     switch (P.family) {
       case kFamily2D:
-        solve_instance<Stencil2D<double, 4>, double>(P, *reinterpret_cast<const Stencil2D<double, 4>*>(op), S, pd,
-                                                     lds, s_phase, epoch);
+        epoch = serve_body<Stencil2D<double, 4>, double>(&P, reinterpret_cast<const Stencil2D<double, 4>*>(op), epoch);
         break;
       case kFamily2DMixed:
-        solve_instance<Stencil2D<float, 4>, float>(P, *reinterpret_cast<const Stencil2D<float, 4>*>(op), S, pf,
-                                                   lds, s_phase, epoch);
+        epoch = serve_body<Stencil2D<float, 4>, float>(&P, reinterpret_cast<const Stencil2D<float, 4>*>(op), epoch);
         break;
       case kFamily3D:
-        solve_instance<Stencil3D<double, 4>, double>(P, *reinterpret_cast<const Stencil3D<double, 4>*>(op), S, pd,
-                                                     lds, s_phase, epoch);
+        epoch = serve_body<Stencil3D<double, 4>, double>(&P, reinterpret_cast<const Stencil3D<double, 4>*>(op), epoch);
         break;
       default:
-        solve_instance<Stencil3D<float, 4>, float>(P, *reinterpret_cast<const Stencil3D<float, 4>*>(op), S, pf,
-                                                   lds, s_phase, epoch);
+        epoch = serve_body<Stencil3D<float, 4>, float>(&P, reinterpret_cast<const Stencil3D<float, 4>*>(op), epoch);
         break;
     }
-    if (vblock() == 0 && threadIdx.x == 0) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (vblock() == 0) P.ctrl->epoch_end = epoch;
       __threadfence();
-      __hip_atomic_store(&Q.done, e + 1, __ATOMIC_RELEASE, KIOPS_AGENT);
+      __hip_atomic_store(&fin[blockIdx.x], e + 1, __ATOMIC_RELEASE, KIOPS_AGENT);
+    }
+    if (local == 0 && threadIdx.x < 64) {
+      wait_all_at_least(fin + (size_t)g * group_size, group_size, e + 1, fin_limit);
+      if (threadIdx.x == 0) __hip_atomic_store(&Q.done, e + 1, __ATOMIC_RELEASE, KIOPS_AGENT);
     }
   }
 }

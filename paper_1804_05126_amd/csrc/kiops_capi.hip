@@ -353,6 +353,8 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   P.bar = reinterpret_cast<Barrier*>(ws + L.bar);
   P.arrive = reinterpret_cast<unsigned*>(ws + L.arrive);
   P.arrive_t = reinterpret_cast<uint64_t*>(ws + L.arrive_t);
+  const char* ps = std::getenv("KIOPS_POLL_SLEEP");   // experiment override
+  P.poll_sleep = ps ? std::max(0, std::min(64, std::atoi(ps))) : 1;
   const char* prof = std::getenv("KIOPS_PROFILE");
   P.profile = (prof && std::atoi(prof) > 0) ? 1 : 0;
   P.H = reinterpret_cast<double*>(ws + L.H);
@@ -730,21 +732,46 @@ int serve_family(const kiops_operator* op) {
   return mixed ? kFamily2DMixed : kFamily2D;
 }
 
-// Per-group fixed state of a server: barrier words, arrival flags and clocks.
-size_t group_area_bytes(int gs) {
-  return align_up(sizeof(Barrier)) + align_up(sizeof(unsigned) * gs) + align_up(sizeof(uint64_t) * 3 * gs);
+constexpr int64_t kGangPointsDefault = 8192;   // grid points per workgroup when sizing a gang
+
+// Groups of group_size workgroups over `per_cu` workgroups per CU (two when
+// the served kernel fits twice on a CU, leaving a wave slot per SIMD and a
+// third of the LDS to other work, else one).
+kiops_status serve_geometry(int group_size, int* gs_out, int* ng_out) {
+  int dev = 0, cus = 0, fit = 0;
+  if (!hip_ok(hipGetDevice(&dev)) ||
+      !hip_ok(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) ||
+      !hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, kernels_serve(), kThreads, 0)) || fit < 1)
+    return KIOPS_ERR_DEVICE;
+  const int per_cu = fit >= 3 ? 2 : 1;
+  const int gs = group_size > 0 ? group_size : 16;
+  if (gs > cus * per_cu || gs % 8 != 0) return KIOPS_ERR_INVALID_ARG;   // groups keep the XCD order of blocks
+  *gs_out = gs;
+  *ng_out = cus * per_cu / gs;
+  return KIOPS_OK;
 }
 
-kiops_status serve_geometry(int group_size, int* gs_out, int* ng_out) {
-  int dev = 0, cus = 0;
-  if (!hip_ok(hipGetDevice(&dev)) ||
-      !hip_ok(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)))
-    return KIOPS_ERR_DEVICE;
-  const int gs = group_size > 0 ? group_size : 16;
-  if (gs > cus) return KIOPS_ERR_INVALID_ARG;
-  *gs_out = gs;
-  *ng_out = cus / gs;   // one workgroup per CU
-  return KIOPS_OK;
+// Fixed part of a server workspace, in this order: one Barrier and one
+// control block per group (a gang uses its first group's), the per-workgroup
+// arrival slots, arrival clocks (3 per workgroup) and finish words, the group
+// queues and one parameter block per group.
+struct ServeLayout {
+  size_t bar, ctrl, arrive, arrive_t, fin, queue, block, pool;
+};
+ServeLayout serve_layout(int gs, int ng) {
+  ServeLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes); return at; };
+  const size_t nwg = (size_t)gs * ng;
+  L.bar = take(sizeof(Barrier) * ng);
+  L.ctrl = take(ctrl_stride() * ng);
+  L.arrive = take(sizeof(unsigned) * nwg);
+  L.arrive_t = take(sizeof(uint64_t) * 3 * nwg);
+  L.fin = take(sizeof(unsigned) * nwg);
+  L.queue = take(sizeof(GroupQueue) * ng);
+  L.block = take((size_t)4096 * ng);
+  L.pool = off;
+  return L;
 }
 
 }  // namespace
@@ -753,7 +780,7 @@ struct kiops_server {
   struct Req {
     kiops_problem pr;
     std::vector<const double*> V;
-    int group = -1;
+    int g0 = -1, k = 0;                  // gang: groups [g0, g0 + k)
     size_t pool_off = 0, pool_bytes = 0;
     int done = 0;
     Ctrl ctrl{};
@@ -761,14 +788,17 @@ struct kiops_server {
   hipStream_t run = nullptr, io = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  int gs = 0, ng = 0;
+  int gs = 0, ng = 0, max_gang = 1;
+  int64_t gang_points = kGangPointsDefault;
   uint64_t clock_hz = 0;
-  size_t area_off = 0, queue_off = 0, ctrl_off = 0, block_off = 0, pool_off = 0, pool_bytes = 0;
+  ServeLayout L{};
+  size_t pool_bytes = 0;
   std::map<size_t, size_t> free_list;   // pool offset -> bytes
   std::deque<int64_t> waiting;
   std::unordered_map<int64_t, Req> reqs;
   std::vector<int64_t> group_req;       // running ticket per group, -1 if free
   std::vector<unsigned> pushed;         // entries pushed per group
+  std::vector<unsigned> last_epoch;     // barrier epoch each group's workgroups have reached
   int64_t next_ticket = 1;
   bool dead = false;
 };
@@ -805,28 +835,46 @@ void pool_free(kiops_server* s, size_t off, size_t bytes) {
   }
 }
 
-size_t request_bytes(const kiops_server* s, const kiops_problem& pr) {
-  int m_min, m_max, max_sub;
-  resolve_options(pr.op, nullptr, &m_min, &m_max, &max_sub);
-  return align_up(make_layout(pr.op, pr.p, pr.q, m_max, s->gs).total);
+// Groups a request runs on: the smallest power of two whose workgroups get at
+// most gang_points grid points each, capped at the largest power of two that
+// fits the launch and kept within the operator's work items (more workgroups
+// than tiles, or z chunks thinner than the march needs, only add overhead).
+int gang_groups(const kiops_server* s, const kiops_operator* op) {
+  const int64_t items = std::max<int64_t>(1, work_tiles(op));
+  const int64_t want = std::min<int64_t>((op->N + s->gang_points - 1) / s->gang_points, items);
+  int k = 1;
+  while ((int64_t)k * s->gs < want && 2 * k <= s->max_gang) k *= 2;
+  if (k > 1 && (int64_t)k * s->gs > items) k /= 2;
+  return k;
 }
 
-// Admit request t on free group g with pool block off.
-kiops_status admit(kiops_server* s, int64_t t, int g, size_t off) {
+size_t request_bytes(const kiops_server* s, const kiops_problem& pr, int k) {
+  int m_min, m_max, max_sub;
+  resolve_options(pr.op, nullptr, &m_min, &m_max, &max_sub);
+  return align_up(make_layout(pr.op, pr.p, pr.q, m_max, k * s->gs).total);
+}
+
+// Admit request t on the free gang [g0, g0 + k) with pool block off.
+kiops_status admit(kiops_server* s, int64_t t, int g0, int k, size_t off, size_t bytes) {
   kiops_server::Req& R = s->reqs[t];
   const kiops_problem& pr = R.pr;
   int m_min, m_max, max_sub;
   resolve_options(pr.op, nullptr, &m_min, &m_max, &max_sub);
-  char* base = s->ws + s->pool_off + off;
-  const Layout L = make_layout(pr.op, pr.p, pr.q, m_max, s->gs);
+  char* base = s->ws + s->L.pool + off;
+  const int nwg = k * s->gs;
+  const int wg0 = g0 * s->gs;
+  const Layout L = make_layout(pr.op, pr.p, pr.q, m_max, nwg);
   KParams P = make_params(pr.op, L, base, pr.tau, pr.p, R.V.data(), pr.tol, pr.m_init, pr.q, m_min, m_max,
                           max_sub, kModeSolve, pr.w);
-  char* area = s->ws + s->area_off + group_area_bytes(s->gs) * g;
-  P.bar = reinterpret_cast<Barrier*>(area);
-  P.arrive = reinterpret_cast<unsigned*>(area + align_up(sizeof(Barrier)));
-  P.arrive_t = reinterpret_cast<uint64_t*>(area + align_up(sizeof(Barrier)) + align_up(sizeof(unsigned) * s->gs));
-  P.ctrl = reinterpret_cast<Ctrl*>(s->ws + s->ctrl_off + ctrl_stride() * g);
+  P.bar = reinterpret_cast<Barrier*>(s->ws + s->L.bar) + g0;
+  P.ctrl = reinterpret_cast<Ctrl*>(s->ws + s->L.ctrl + ctrl_stride() * g0);
+  P.arrive = reinterpret_cast<unsigned*>(s->ws + s->L.arrive) + wg0;
+  P.arrive_t = reinterpret_cast<uint64_t*>(s->ws + s->L.arrive_t) + 3 * (size_t)wg0;
   P.family = serve_family(pr.op);
+  P.wg0 = wg0;
+  unsigned e0 = 0;
+  for (int g = g0; g < g0 + k; ++g) e0 = std::max(e0, s->last_epoch[g]);
+  P.epoch0 = e0;
   alignas(256) unsigned char blk[4096];
   std::memset(blk, 0, sizeof(blk));
   std::memcpy(blk, &P, sizeof(KParams));
@@ -835,22 +883,57 @@ kiops_status admit(kiops_server* s, int64_t t, int g, size_t off) {
   Ctrl c{};
   c.phase = kPhaseDone;
   c.status = KIOPS_ERR_DEVICE;
-  unsigned char* dblk = reinterpret_cast<unsigned char*>(s->ws + s->block_off + (size_t)4096 * g);
-  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->queue_off) + g;
-  const unsigned e = s->pushed[g];
-  const unsigned char* ptr = dblk;
-  const unsigned tail = e + 1;
-  if (!hip_ok(hipMemcpyAsync(P.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s->io)) ||
-      !hip_ok(hipMemcpyAsync(dblk, blk, sizeof(blk), hipMemcpyHostToDevice, s->io)) ||
-      !hip_ok(hipMemcpyAsync(&dq->blocks[e % kGroupQueueLen], &ptr, sizeof(ptr), hipMemcpyHostToDevice, s->io)) ||
-      !hip_ok(hipMemcpyAsync(&dq->tail, &tail, sizeof(tail), hipMemcpyHostToDevice, s->io)) ||
-      !hip_ok(hipStreamSynchronize(s->io)))
-    return KIOPS_ERR_DEVICE;
-  s->pushed[g] = tail;
-  s->group_req[g] = t;
-  R.group = g;
+  if (!hip_ok(hipMemcpyAsync(P.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s->io))) return KIOPS_ERR_DEVICE;
+  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->L.queue);
+  std::vector<const unsigned char*> ptrs(k);
+  std::vector<unsigned> tails(k);
+  for (int i = 0; i < k; ++i) {
+    const int g = g0 + i;
+    unsigned char* dblk = reinterpret_cast<unsigned char*>(s->ws + s->L.block + (size_t)4096 * g);
+    ptrs[i] = dblk;
+    tails[i] = s->pushed[g] + 1;
+    if (!hip_ok(hipMemcpyAsync(dblk, blk, sizeof(blk), hipMemcpyHostToDevice, s->io)) ||
+        !hip_ok(hipMemcpyAsync(&dq[g].blocks[s->pushed[g] % kGroupQueueLen], &ptrs[i], sizeof(ptrs[i]),
+                               hipMemcpyHostToDevice, s->io)))
+      return KIOPS_ERR_DEVICE;
+  }
+  // publish after every block of the gang is in place
+  for (int i = 0; i < k; ++i)
+    if (!hip_ok(hipMemcpyAsync(&dq[g0 + i].tail, &tails[i], sizeof(unsigned), hipMemcpyHostToDevice, s->io)))
+      return KIOPS_ERR_DEVICE;
+  if (!hip_ok(hipStreamSynchronize(s->io))) return KIOPS_ERR_DEVICE;
+  for (int i = 0; i < k; ++i) {
+    s->pushed[g0 + i] = tails[i];
+    s->group_req[g0 + i] = t;
+  }
+  R.g0 = g0;
+  R.k = k;
   R.pool_off = off;
+  R.pool_bytes = bytes;
   return KIOPS_OK;
+}
+
+// First aligned free run of k groups outside [rlo, rhi), or -1.
+int free_gang(const kiops_server* s, int k, int rlo, int rhi) {
+  for (int g0 = 0; g0 + k <= s->ng; g0 += k) {
+    if (g0 < rhi && rlo < g0 + k) continue;
+    bool ok = true;
+    for (int g = g0; g < g0 + k && ok; ++g) ok = s->group_req[g] < 0;
+    if (ok) return g0;
+  }
+  return -1;
+}
+
+// Aligned run of k groups with the fewest busy groups (reserved for the
+// request at the head of the queue so that smaller ones cannot starve it).
+int reserve_gang(const kiops_server* s, int k) {
+  int best = 0, best_busy = k + 1;
+  for (int g0 = 0; g0 + k <= s->ng; g0 += k) {
+    int busy = 0;
+    for (int g = g0; g < g0 + k; ++g) busy += s->group_req[g] >= 0;
+    if (busy < best_busy) { best = g0; best_busy = busy; }
+  }
+  return best;
 }
 
 }  // namespace
@@ -1089,23 +1172,20 @@ kiops_status kiops_server_fixed_bytes(int group_size, size_t* bytes, int* groups
   int gs = 0, ng = 0;
   kiops_status st = serve_geometry(group_size, &gs, &ng);
   if (st != KIOPS_OK) return st;
-  const size_t fixed = align_up(group_area_bytes(gs) * ng) + align_up(sizeof(GroupQueue) * ng) +
-                       align_up(ctrl_stride() * ng) + align_up((size_t)4096 * ng);
-  if (bytes) *bytes = fixed;
+  if (bytes) *bytes = serve_layout(gs, ng).pool;
   if (groups) *groups = ng;
   return KIOPS_OK;
 }
 
-kiops_status kiops_server_create(int group_size, void* workspace, size_t workspace_bytes, void* run_stream,
-                                 void* io_stream, kiops_server** out) {
+kiops_status kiops_server_create(int group_size, int64_t points_per_workgroup, void* workspace,
+                                 size_t workspace_bytes, void* run_stream, void* io_stream, kiops_server** out) {
   if (!out || !workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return KIOPS_ERR_INVALID_ARG;
-  if (run_stream == io_stream) return KIOPS_ERR_INVALID_ARG;
+  if (run_stream == io_stream || points_per_workgroup < 0) return KIOPS_ERR_INVALID_ARG;
   int gs = 0, ng = 0;
   kiops_status st = serve_geometry(group_size, &gs, &ng);
   if (st != KIOPS_OK) return st;
-  size_t fixed = 0;
-  kiops_server_fixed_bytes(gs, &fixed, nullptr);
-  if (workspace_bytes <= fixed) return KIOPS_ERR_OUT_OF_MEMORY;
+  const ServeLayout SL = serve_layout(gs, ng);
+  if (workspace_bytes <= SL.pool) return KIOPS_ERR_OUT_OF_MEMORY;
   kiops_server* s = new (std::nothrow) kiops_server();
   if (!s) return KIOPS_ERR_OUT_OF_MEMORY;
   s->run = reinterpret_cast<hipStream_t>(run_stream);
@@ -1114,32 +1194,37 @@ kiops_status kiops_server_create(int group_size, void* workspace, size_t workspa
   s->ws_bytes = workspace_bytes;
   s->gs = gs;
   s->ng = ng;
+  while (2 * s->max_gang <= ng) s->max_gang *= 2;
+  if (points_per_workgroup > 0) s->gang_points = points_per_workgroup;
   int dev = 0, khz = 0;
   hipGetDevice(&dev);
   if (!hip_ok(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) || khz <= 0) khz = 100000;
   s->clock_hz = (uint64_t)khz * 1000ull;
-  s->area_off = 0;
-  s->queue_off = align_up(group_area_bytes(gs) * ng);
-  s->ctrl_off = s->queue_off + align_up(sizeof(GroupQueue) * ng);
-  s->block_off = s->ctrl_off + align_up(ctrl_stride() * ng);
-  s->pool_off = s->block_off + align_up((size_t)4096 * ng);
-  s->pool_bytes = (workspace_bytes - s->pool_off) / kAlign * kAlign;
+  s->L = SL;
+  s->pool_bytes = (workspace_bytes - SL.pool) / kAlign * kAlign;
   s->free_list[0] = s->pool_bytes;
   s->group_req.assign(ng, -1);
   s->pushed.assign(ng, 0);
+  s->last_epoch.assign(ng, 0);
   std::vector<GroupQueue> q(ng);
   for (auto& Q : q) {
     std::memset(&Q, 0, sizeof(GroupQueue));
     Q.idle_limit = s->clock_hz * 600ull;   // a launch nobody feeds ends after ten minutes
+    // an idle group polls its queue every few microseconds, not continuously:
+    // hundreds of polling workgroups slow the memory accesses of busy ones
+    const char* is = std::getenv("KIOPS_IDLE_SLEEP");   // experiment override
+    Q.idle_sleep = is ? (unsigned)std::max(0, std::min(64, std::atoi(is))) : 4u;
   }
-  if (!hip_ok(hipMemsetAsync(s->ws + s->area_off, 0, s->queue_off - s->area_off, s->io)) ||
-      !hip_ok(hipMemcpyAsync(s->ws + s->queue_off, q.data(), sizeof(GroupQueue) * ng, hipMemcpyHostToDevice, s->io)) ||
+  if (!hip_ok(hipMemsetAsync(s->ws, 0, SL.queue, s->io)) ||
+      !hip_ok(hipMemcpyAsync(s->ws + SL.queue, q.data(), sizeof(GroupQueue) * ng, hipMemcpyHostToDevice, s->io)) ||
       !hip_ok(hipStreamSynchronize(s->io))) {
     delete s;
     return KIOPS_ERR_DEVICE;
   }
-  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->queue_off);
-  void* args[] = {&dq, &s->gs};
+  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + SL.queue);
+  unsigned* fin = reinterpret_cast<unsigned*>(s->ws + SL.fin);
+  uint64_t fin_limit = s->clock_hz * 60ull;
+  void* args[] = {&dq, &fin, &s->gs, &fin_limit};
   if (!hip_ok(hipLaunchCooperativeKernel(kernels_serve(), dim3(ng * gs), dim3(kThreads), args, 0, s->run))) {
     delete s;
     return KIOPS_ERR_DEVICE;
@@ -1157,7 +1242,7 @@ kiops_status kiops_server_submit(kiops_server* s, const kiops_problem* pr, int64
   kiops_status st = check_vectors(pr->op, pr->p, pr->V, pr->w);
   if (st != KIOPS_OK) return st;
   if (serve_family(pr->op) < 0) return KIOPS_ERR_UNSUPPORTED;
-  if (request_bytes(s, *pr) > s->pool_bytes) return KIOPS_ERR_BUDGET;
+  if (request_bytes(s, *pr, gang_groups(s, pr->op)) > s->pool_bytes) return KIOPS_ERR_BUDGET;
   kiops_server::Req R;
   R.pr = *pr;
   R.V.assign(pr->V, pr->V + pr->p + 1);
@@ -1174,47 +1259,75 @@ kiops_status kiops_server_progress(kiops_server* s, int* running, int* waiting) 
   if (s->dead) return KIOPS_ERR_DEVICE;
   // the done and exited words of every group queue
   std::vector<unsigned> words(2 * s->ng, 0);
-  const GroupQueue* dq = reinterpret_cast<const GroupQueue*>(s->ws + s->queue_off);
+  const GroupQueue* dq = reinterpret_cast<const GroupQueue*>(s->ws + s->L.queue);
   if (!hip_ok(hipMemcpy2DAsync(words.data(), 2 * sizeof(unsigned), &dq->done, sizeof(GroupQueue),
                                2 * sizeof(unsigned), s->ng, hipMemcpyDeviceToHost, s->io)) ||
       !hip_ok(hipStreamSynchronize(s->io)))
     return KIOPS_ERR_DEVICE;
-  {
-    for (int g = 0; g < s->ng; ++g) {
-      if (words[2 * g + 1]) {   // a group has left: its launch is over
-        if (std::getenv("KIOPS_DEBUG")) std::fprintf(stderr, "kiops: server group %d has exited\n", g);
-        s->dead = true;
-        return KIOPS_ERR_DEVICE;
-      }
-      const int64_t t = s->group_req[g];
-      if (t < 0 || words[2 * g] < s->pushed[g]) continue;
-      kiops_server::Req& R = s->reqs[t];
-      if (!hip_ok(hipMemcpyAsync(&R.ctrl, s->ws + s->ctrl_off + ctrl_stride() * g, sizeof(Ctrl),
-                                 hipMemcpyDeviceToHost, s->io)) ||
-          !hip_ok(hipStreamSynchronize(s->io)))
-        return KIOPS_ERR_DEVICE;
-      R.done = 1;
-      pool_free(s, R.pool_off, request_bytes(s, R.pr));
-      s->group_req[g] = -1;
+  for (int g = 0; g < s->ng; ++g) {
+    if (words[2 * g + 1]) {   // a group has left: its launch is over
+      if (std::getenv("KIOPS_DEBUG")) std::fprintf(stderr, "kiops: server group %d has exited\n", g);
+      s->dead = true;
+      return KIOPS_ERR_DEVICE;
     }
   }
-  // admit waiting requests in arrival order (a request that does not fit the
-  // pool yet lets at most eight later ones go first)
-  for (size_t k = 0; k < s->waiting.size() && k < 9;) {
-    int g = -1;
-    for (int h = 0; h < s->ng; ++h)
-      if (s->group_req[h] < 0) { g = h; break; }
-    if (g < 0) break;
-    const int64_t t = s->waiting[k];
+  // a request is finished when every group of its gang has reported it
+  for (int g0 = 0; g0 < s->ng; ++g0) {
+    const int64_t t = s->group_req[g0];
+    if (t < 0) continue;
+    kiops_server::Req& R = s->reqs[t];
+    if (R.g0 != g0) continue;
+    bool fin = true;
+    for (int g = g0; g < g0 + R.k && fin; ++g) fin = words[2 * g] >= s->pushed[g];
+    if (!fin) continue;
+    unsigned abort_word = 0;
+    const Barrier* bar = reinterpret_cast<const Barrier*>(s->ws + s->L.bar) + g0;
+    if (!hip_ok(hipMemcpyAsync(&R.ctrl, s->ws + s->L.ctrl + ctrl_stride() * g0, sizeof(Ctrl),
+                               hipMemcpyDeviceToHost, s->io)) ||
+        !hip_ok(hipMemcpyAsync(&abort_word, &bar->abort, sizeof(unsigned), hipMemcpyDeviceToHost, s->io)) ||
+        !hip_ok(hipStreamSynchronize(s->io)))
+      return KIOPS_ERR_DEVICE;
+    if (abort_word) {   // a bounded wait expired: epochs and queues can no longer be trusted
+      R.ctrl.status = KIOPS_ERR_DEVICE;
+      s->dead = true;
+    }
+    R.done = 1;
+    pool_free(s, R.pool_off, R.pool_bytes);
+    for (int g = g0; g < g0 + R.k; ++g) {
+      s->group_req[g] = -1;
+      s->last_epoch[g] = R.ctrl.epoch_end;
+    }
+  }
+  if (s->dead) return KIOPS_ERR_DEVICE;
+  // admit waiting requests in arrival order; when the head of the queue finds
+  // no free gang, its gang is reserved and at most eight later requests may go
+  // first elsewhere
+  int rlo = 0, rhi = 0;
+  for (size_t i = 0; i < s->waiting.size() && i < 9;) {
+    const int64_t t = s->waiting[i];
+    const kiops_problem& pr = s->reqs[t].pr;
+    const int k = gang_groups(s, pr.op);
+    const int g0 = free_gang(s, k, rlo, rhi);
+    const size_t bytes = request_bytes(s, pr, k);
     size_t off = 0;
-    if (!pool_alloc(s, request_bytes(s, s->reqs[t].pr), &off)) { ++k; continue; }
-    kiops_status st = admit(s, t, g, off);
-    if (st != KIOPS_OK) return st;
-    s->waiting.erase(s->waiting.begin() + k);
+    if (g0 >= 0 && pool_alloc(s, bytes, &off)) {
+      kiops_status st = admit(s, t, g0, k, off, bytes);
+      if (st != KIOPS_OK) return st;
+      s->waiting.erase(s->waiting.begin() + i);
+      continue;
+    }
+    if (i == 0 && g0 < 0) {
+      rlo = reserve_gang(s, k);
+      rhi = rlo + k;
+    }
+    ++i;
   }
   if (running) {
     int r = 0;
-    for (int g = 0; g < s->ng; ++g) r += s->group_req[g] >= 0;
+    for (int g = 0; g < s->ng; ++g) {
+      const int64_t t = s->group_req[g];
+      r += t >= 0 && s->reqs[t].g0 == g;
+    }
     *running = r;
   }
   if (waiting) *waiting = (int)s->waiting.size();
@@ -1229,7 +1342,7 @@ kiops_status kiops_server_result(kiops_server* s, int64_t ticket, int* done, kio
   if (it->second.done) {
     if (stats) {
       std::memset(stats, 0, sizeof(*stats));
-      fill_stats(it->second.ctrl, s->gs, (double)s->clock_hz, stats);
+      fill_stats(it->second.ctrl, it->second.k * s->gs, (double)s->clock_hz, stats);
     }
     s->reqs.erase(it);
   }
@@ -1239,7 +1352,7 @@ kiops_status kiops_server_result(kiops_server* s, int64_t ticket, int* done, kio
 kiops_status kiops_server_destroy(kiops_server* s) {
   if (!s) return KIOPS_ERR_INVALID_ARG;
   const unsigned one = 1;
-  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->queue_off);
+  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->L.queue);
   kiops_status st = KIOPS_OK;
   for (int g = 0; g < s->ng; ++g)
     if (!hip_ok(hipMemcpyAsync(&dq[g].closed, &one, sizeof(one), hipMemcpyHostToDevice, s->io))) st = KIOPS_ERR_DEVICE;

@@ -37,8 +37,9 @@ struct Stencil2D {
   static constexpr int kLdsT = RX * RY + SX * SY;  // elements of T
   static constexpr int kLdsDoubles = (int)((kLdsT * sizeof(T) + 7) / 8);
   static constexpr bool kTwoPhase = false;   // one fused pass per Krylov step
-  // occupancy target: the register footprint of a tile's loads grows with PB
-  static constexpr int kWavesPerEU = (PB >= 4 && sizeof(T) == 8) ? 3 : 4;
+  // register budget of 168 VGPRs (three waves per SIMD): a tile's loads are
+  // held in registers, and at 128 the pass spills to scratch
+  static constexpr int kWavesPerEU = 3;
 
   int64_t N;
   int nx, ny, tiles_x, ntiles;

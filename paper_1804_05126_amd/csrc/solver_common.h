@@ -67,7 +67,8 @@ struct Ctrl {
   int32_t have_old, m_old;
   double tau_old, eps_old, omega_old;
   // ---- statistics
-  int32_t substeps, rejections, expms, breakdowns, attempts, pad1;
+  int32_t substeps, rejections, expms, breakdowns, attempts;
+  uint32_t epoch_end;          // served form: grid-barrier epoch when the solve ended
   int64_t matvecs;
   double last_omega, alg_bytes;
   double s_last;
@@ -95,6 +96,9 @@ struct KParams {
   int mode, mixed, nwg, ndot_stride;
   int profile;                 // record per-workgroup arrival times (diagnostics)
   int family;                  // served form: operator family of the request (kFamily*)
+  int wg0;                     // served form: first workgroup of the gang running the solve
+  unsigned epoch0;             // served form: grid-barrier epoch the solve starts from
+  int poll_sleep;              // barrier polls: s_sleep(2) repeats between two reads of a flag
   double T_end, tol;
   double elem_bytes;           // bytes per basis element (8 or 4)
   double coef_streams;         // per-cell coefficient arrays the operator reads
@@ -134,7 +138,9 @@ struct GroupQueue {
   uint64_t idle_limit;      // wall-clock ticks a group waits for an entry
   unsigned exit_reason;     // why the group left: 1 closed, 2 idle (device)
   unsigned exit_entry;      // the entry it was waiting for then (device)
-  uint64_t pad1[12];        // one 128-byte line for the words above
+  unsigned idle_sleep;      // s_sleep(127) repeats between two polls of an idle group
+  unsigned pad0;
+  uint64_t pad1[11];        // one 128-byte line for the words above
   const unsigned char* blocks[kGroupQueueLen];
 };
 

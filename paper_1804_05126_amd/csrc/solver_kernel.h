@@ -89,7 +89,7 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
       const uint64_t t0 = (uint64_t)wall_clock64();
       for (unsigned spins = 1;; ++spins) {
         if (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) break;
-        __builtin_amdgcn_s_sleep(2);
+        for (int z = 0; z < P.poll_sleep; ++z) __builtin_amdgcn_s_sleep(2);
         if ((spins & 63u) == 0 && spin_expired(b, t0, P.spin_limit)) break;
       }
       if (P.profile) P.arrive_t[P.nwg + vblock()] = (uint64_t)wall_clock64();
@@ -104,6 +104,7 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
     for (unsigned w = 1 + threadIdx.x; w < (unsigned)P.nwg; w += kThreads)
       ok &= (__hip_atomic_load(&P.arrive[w], __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) ? 1 : 0;
     if (__syncthreads_and(ok)) break;
+    for (int z = 0; z < P.poll_sleep; ++z) __builtin_amdgcn_s_sleep(2);
     if ((spins & 15u) == 0) {
       if (threadIdx.x == 0) S.expired = spin_expired(b, t0, P.spin_limit) ? 1 : 0;   // thread 0 decides
       __syncthreads();
@@ -815,6 +816,7 @@ __device__ inline long long wait_entry(GroupQueue& Q, unsigned e) {
       }
       result = -1;
     } else {
+      for (unsigned z = 0; z < Q.idle_sleep; ++z) __builtin_amdgcn_s_sleep(127);
       __builtin_amdgcn_s_sleep(8);
     }
   }
@@ -891,6 +893,17 @@ kiops_solve_kernel(const KParams* __restrict__ Pp, const Op* __restrict__ opp) {
   solve_instance<Op, T>(*Pp, *opp, S, pctx, lds, s_phase, epoch);
 }
 
+// A solve whose parameter block and operator struct are read-only for its
+// whole duration (restrict, kept through inlining), so that their fields can
+// stay in scalar registers across the stores of the passes.
+template <class Op, typename T>
+__device__ __forceinline__ void solve_block(const KParams* __restrict__ Pp, const Op* __restrict__ opp,
+                                            SmallState& S, PassCtx<T>& pctx, double* lds, int& s_phase,
+                                            unsigned& epoch) {
+  const Op op = load_uniform(opp);   // operator fields in scalar registers for the passes
+  solve_instance<Op, T>(*Pp, op, S, pctx, lds, s_phase, epoch);
+}
+
 // Groups of workgroups, each running the solves queued for it one after
 // another (batched and served forms).  Group g is workgroups
 // [g * group_size, (g+1) * group_size); its queue lists parameter blocks
@@ -923,10 +936,11 @@ kiops_group_kernel(GroupQueue* __restrict__ queues, int group_size) {
       if (vblock() == 0 && threadIdx.x == 0) __hip_atomic_store(&Q.exited, 1u, __ATOMIC_RELEASE, KIOPS_AGENT);
       return;
     }
-    const unsigned char* blk = Q.blocks[entry % kGroupQueueLen];
-    const KParams& P = *reinterpret_cast<const KParams*>(blk);
-    const Op& op = *reinterpret_cast<const Op*>(blk + 2048);
-    solve_instance<Op, T>(P, op, S, pctx, lds, s_phase, epoch);
+    // the block pointer is wave-uniform (made explicit, so that the block's
+    // fields are read with scalar loads and buffer resources stay scalar)
+    const unsigned char* blk = uniform(Q.blocks[uniform((int)(entry % kGroupQueueLen))]);
+    solve_block<Op, T>(reinterpret_cast<const KParams*>(blk), reinterpret_cast<const Op*>(blk + 2048), S, pctx,
+                       lds, s_phase, epoch);
     if (vblock() == 0 && threadIdx.x == 0) {
       __threadfence();
       __hip_atomic_store(&Q.done, e + 1, __ATOMIC_RELEASE, KIOPS_AGENT);

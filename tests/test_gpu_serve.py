@@ -109,3 +109,33 @@ def test_served_budget_admission():
         srv.close()
     for t in (t1, t2):
         assert rel(res[t][1], ref_big.cpu().numpy()) <= 1e-8
+
+
+def test_served_gangs_match_alone():
+    """Requests large enough to run on gangs of several groups (2, 4, 8, ... of
+    16 workgroups), mixed with one-group requests, all in flight together."""
+    import paper_1804_05126_amd as K
+    prs = [W.adr2d_problem(s, p, tau, seed=5100 + i) for i, (s, p, tau) in
+           enumerate([(96, 2, 1e-3), (300, 3, 2e-4), (40, 1, 1e-2), (512, 2, 1e-4), (128, 4, 5e-4)])]
+    prs += [W.diffusion3d_problem(s, 2, 2e-4, seed=5200 + s, tol=1e-8) for s in (24, 48, 64)]
+    ins = _inputs(prs)
+    alone = []
+    for pr, (op, vecs) in zip(prs, ins):
+        w, st, status = K.phi_combination(op, pr.tau, vecs, tol=pr.tol)
+        assert status == 0
+        alone.append(w.cpu().numpy())
+    srv = K.Server(pool_bytes=8 << 30, group_size=16, points_per_workgroup=1024)
+    announce(f"served gangs: {srv.groups} groups of 16")
+    try:
+        tickets = [srv.submit(op, pr.tau, vecs, tol=pr.tol) for pr, (op, vecs) in zip(prs, ins)]
+        res = _drain(srv, tickets)
+    finally:
+        srv.close()
+    sizes = []
+    for pr, a, t in zip(prs, alone, tickets):
+        st, w = res[t]
+        assert st["status"] == 0
+        sizes.append(st["grid_blocks"])
+        assert rel(w, a) <= 2e-8, (pr.name, rel(w, a))
+    announce(f"  gang sizes (workgroups): {sizes}")
+    assert max(sizes) >= 64 and min(sizes) == 16
