@@ -130,6 +130,8 @@ typedef struct {
   double release_max_s, release_mean_s;
   int32_t status;          /* the solve's own status (useful for batched problems) */
   int32_t reserved2;
+  double time_reduce_s;    /* part of time_epilogue_s: reductions of the per-workgroup partial sums of passes */
+  double time_publish_s;   /* part of time_epilogue_s: copies of the control block after passes */
 } kiops_stats;
 
 typedef struct kiops_operator kiops_operator;

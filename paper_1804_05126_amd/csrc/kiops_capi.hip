@@ -50,6 +50,7 @@ __global__ void kiops_reset_kernel(Barrier* b, Ctrl* c, unsigned* arrive, int nw
     c->status = KIOPS_OK;
     c->t_work = c->t_wait = c->t_epi = 0;
     c->t_expm = c->t_arrive_max = c->t_arrive_mean = c->n_barriers = 0;
+    c->t_red = c->t_pub = 0;
     c->t_release_max = c->t_release_mean = 0;
   }
 }
@@ -154,7 +155,8 @@ kiops_status grid_size(const kiops_operator* op, int p, int* nwg) {
   // The 5-point tile pass runs best with two workgroups per CU (measured at
   // 2048^2: 110 us per Krylov step against 120 us with three); the marching
   // 7-point pass with all that fit.
-  if (!uses_3d(op)) per_cu = std::min(per_cu, 2);
+  const char* pc = std::getenv("KIOPS_PER_CU");   // experiment override of the 2-D choice
+  if (!uses_3d(op)) per_cu = std::min(per_cu, pc && std::atoi(pc) > 0 ? std::atoi(pc) : 2);
   int64_t g = (int64_t)per_cu * op->cus;
   const char* ov = std::getenv("KIOPS_GRID");   // experiment override, capped by co-residency
   if (ov && std::atoi(ov) > 0) g = std::min<int64_t>(g, std::atoi(ov));
@@ -434,7 +436,9 @@ kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, c
     return KIOPS_ERR_DEVICE;
   {
     void* args[] = {&dP, &dOp};
-    e = hipLaunchCooperativeKernel(fn, dim3(L.nwg), dim3(kThreads), args, 0, op->stream);
+    const char* pad = std::getenv("KIOPS_PAD_LDS");   // experiment: unused dynamic LDS per workgroup
+    const unsigned dyn = pad ? (unsigned)std::max(0, std::min(65536, std::atoi(pad))) : 0u;
+    e = hipLaunchCooperativeKernel(fn, dim3(L.nwg), dim3(kThreads), args, dyn, op->stream);
   }
   if (!hip_ok(e)) return KIOPS_ERR_DEVICE;
   Barrier hb{};
@@ -470,6 +474,8 @@ void fill_stats(const Ctrl& c, int nwg, double clock_hz, kiops_stats* st) {
   st->alg_bytes = c.alg_bytes;
   st->beta_last = c.beta;
   st->status = c.status;
+  st->time_reduce_s = (double)c.t_red / clock_hz;
+  st->time_publish_s = (double)c.t_pub / clock_hz;
 }
 
 kiops_status check_vectors(const kiops_operator* op, int p, const double* const* V, const double* w) {

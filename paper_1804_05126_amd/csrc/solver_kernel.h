@@ -181,6 +181,8 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
     P.ctrl->t_release_max = C.t_release_max;
     P.ctrl->t_release_mean = C.t_release_mean;
     P.ctrl->n_barriers = C.n_barriers;
+    P.ctrl->t_red = C.t_red;
+    P.ctrl->t_pub = C.t_pub;
     __threadfence();
     __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
   }
@@ -479,7 +481,9 @@ __device__ inline int step_advance(SmallState& S, int k, int flo_next) {
 // vectors come from a separate phase first (epilogue_dots).
 __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, double* lds) {
   Ctrl& C = S.C;
+  const uint64_t tr0 = (uint64_t)wall_clock64();
   reduce_partials(P, S.red, lds, P.nwg);
+  if (threadIdx.x == 0) C.t_red += (uint64_t)wall_clock64() - tr0;
   if (C.q == 0 && C.kp > 1) {                 // full window: inner products first
     if (threadIdx.x == 0) C.phase = kPhaseDots;
     __syncthreads();
@@ -546,7 +550,9 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
   __syncthreads();
   const int action = S.action;
   if (action == 1 || action == 2) attempt_end(P, S, S.jj, action == 2, lds);
+  const uint64_t tp0 = (uint64_t)wall_clock64();
   publish(P, S);
+  if (threadIdx.x == 0) S.C.t_pub += (uint64_t)wall_clock64() - tp0;
 }
 
 // Epilogue after the inner-product phase of a full-window step (q = 0): the
@@ -622,7 +628,9 @@ __device__ __noinline__ void epilogue_dots(const KParams& P, SmallState& S, doub
   }
   const int action = S.action;
   if (action == 1 || action == 2) attempt_end(P, S, S.jj, action == 2, lds);
+  const uint64_t tp0 = (uint64_t)wall_clock64();
   publish(P, S);
+  if (threadIdx.x == 0) S.C.t_pub += (uint64_t)wall_clock64() - tp0;
 }
 
 // Epilogue after the gather: advance T_now (Alg. 1) and start the next substep.
@@ -839,6 +847,7 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
     S.C.t_work = S.C.t_wait = S.C.t_epi = 0;
     S.C.t_expm = S.C.t_arrive_max = S.C.t_arrive_mean = S.C.n_barriers = 0;
     S.C.t_release_max = S.C.t_release_mean = 0;
+    S.C.t_red = S.C.t_pub = 0;
     S.C.t_last = (uint64_t)wall_clock64();
   }
 
