@@ -132,6 +132,7 @@ typedef struct {
   int32_t reserved2;
   double time_reduce_s;    /* part of time_epilogue_s: reductions of the per-workgroup partial sums of passes */
   double time_publish_s;   /* part of time_epilogue_s: copies of the control block after passes */
+  double time_serial_s;    /* part of time_epilogue_s: normalisation, H column and next coefficients */
 } kiops_stats;
 
 typedef struct kiops_operator kiops_operator;

@@ -50,7 +50,7 @@ __global__ void kiops_reset_kernel(Barrier* b, Ctrl* c, unsigned* arrive, int nw
     c->status = KIOPS_OK;
     c->t_work = c->t_wait = c->t_epi = 0;
     c->t_expm = c->t_arrive_max = c->t_arrive_mean = c->n_barriers = 0;
-    c->t_red = c->t_pub = 0;
+    c->t_red = c->t_pub = c->t_ser = 0;
     c->t_release_max = c->t_release_mean = 0;
   }
 }
@@ -476,6 +476,7 @@ void fill_stats(const Ctrl& c, int nwg, double clock_hz, kiops_stats* st) {
   st->status = c.status;
   st->time_reduce_s = (double)c.t_red / clock_hz;
   st->time_publish_s = (double)c.t_pub / clock_hz;
+  st->time_serial_s = (double)c.t_ser / clock_hz;
 }
 
 kiops_status check_vectors(const kiops_operator* op, int p, const double* const* V, const double* w) {

@@ -78,7 +78,8 @@ struct Ctrl {
   // optional profile: small exponentials, latest / mean arrival after a release
   uint64_t t_expm, t_arrive_max, t_arrive_mean, n_barriers;
   uint64_t t_release_max, t_release_mean;   // delay until a workgroup sees the release
-  uint64_t t_red, t_pub;       // epilogues of passes: partial-sum reduction, control-block copy
+  uint64_t t_red, t_pub, t_ser;   // epilogues of passes: partial-sum reduction, control-block copy,
+                                  // serial normalisation and coefficients
 };
 
 // Release word and abort flag on separate 128-byte lines: every workgroup

@@ -183,6 +183,7 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
     P.ctrl->n_barriers = C.n_barriers;
     P.ctrl->t_red = C.t_red;
     P.ctrl->t_pub = C.t_pub;
+    P.ctrl->t_ser = C.t_ser;
     __threadfence();
     __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
   }
@@ -491,6 +492,7 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
     return;
   }
   if (threadIdx.x == 0) {
+    const uint64_t ts0 = (uint64_t)wall_clock64();
     const int k = C.kp;
     const int dlo = C.dlo;
     const int p = C.p;
@@ -546,6 +548,7 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
     }
     S.action = action;
     S.jj = k - 1;
+    C.t_ser += (uint64_t)wall_clock64() - ts0;
   }
   __syncthreads();
   const int action = S.action;
@@ -847,7 +850,7 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
     S.C.t_work = S.C.t_wait = S.C.t_epi = 0;
     S.C.t_expm = S.C.t_arrive_max = S.C.t_arrive_mean = S.C.n_barriers = 0;
     S.C.t_release_max = S.C.t_release_mean = 0;
-    S.C.t_red = S.C.t_pub = 0;
+    S.C.t_red = S.C.t_pub = S.C.t_ser = 0;
     S.C.t_last = (uint64_t)wall_clock64();
   }
 
