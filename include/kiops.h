@@ -130,9 +130,10 @@ typedef struct {
   double release_max_s, release_mean_s;
   int32_t status;          /* the solve's own status (useful for batched problems) */
   int32_t reserved2;
-  double time_reduce_s;    /* part of time_epilogue_s: reductions of the per-workgroup partial sums of passes */
-  double time_publish_s;   /* part of time_epilogue_s: copies of the control block after passes */
-  double time_serial_s;    /* part of time_epilogue_s: normalisation, H column and next coefficients */
+  /* With KIOPS_PROFILE=1 only (else 0): parts of time_epilogue_s after passes */
+  double time_reduce_s;    /* reductions of the per-workgroup partial sums */
+  double time_publish_s;   /* copies of the control block */
+  double time_serial_s;    /* normalisation, H column and next coefficients (thread 0) */
 } kiops_stats;
 
 typedef struct kiops_operator kiops_operator;

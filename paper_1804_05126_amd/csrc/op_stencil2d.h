@@ -37,9 +37,11 @@ struct Stencil2D {
   static constexpr int kLdsT = RX * RY + SX * SY;  // elements of T
   static constexpr int kLdsDoubles = (int)((kLdsT * sizeof(T) + 7) / 8);
   static constexpr bool kTwoPhase = false;   // one fused pass per Krylov step
-  // register budget of 168 VGPRs (three waves per SIMD): a tile's loads are
-  // held in registers, and at 128 the pass spills to scratch
-  static constexpr int kWavesPerEU = 3;
+  // register budget of 256 VGPRs (two waves per SIMD, the two workgroups per
+  // CU the grid uses): a tile's loads are held in registers, and at 168 or 128
+  // the pass spills to scratch in its loop (measured: 3-4% slower per step at
+  // 168, more after unrelated code changes shift the allocation)
+  static constexpr int kWavesPerEU = 2;
 
   int64_t N;
   int nx, ny, tiles_x, ntiles;
@@ -83,7 +85,8 @@ struct Stencil2D {
     const __amdgpu_buffer_rsrc_t rsW = make_rsrc(first ? w : nullptr, (uint64_t)N * 8);
     const __amdgpu_buffer_rsrc_t rsr = make_rsrc(r, nb);
     const __amdgpu_buffer_rsrc_t rsOut = make_rsrc(c.write_out ? Rout : nullptr, nb);
-    const __amdgpu_buffer_rsrc_t rsU = make_rsrc(c.store_u ? ubuf : nullptr, nb);
+    const bool store_u = uniform(c.store_u) != 0;   // full window only: no store otherwise
+    const __amdgpu_buffer_rsrc_t rsU = make_rsrc(store_u ? ubuf : nullptr, nb);
     __amdgpu_buffer_rsrc_t rsB[PB > 0 ? PB : 1];
 #pragma unroll
     for (int k = 0; k < PB; ++k) rsB[k] = make_rsrc(k < c.p ? B[k] : nullptr, nb);
@@ -200,7 +203,7 @@ struct Stencil2D {
         U = fma(wC + rv[i], X, U);
         U += bcur[i];
         buf_st(rsOut, valid ? goff[i] : kNoOffset, X);
-        buf_st(rsU, valid ? goff[i] : kNoOffset, U);
+        if (store_u) buf_st(rsU, valid ? goff[i] : kNoOffset, U);
         const double Xd = valid ? (double)X : 0.0, Ud = valid ? (double)U : 0.0;
         acc.RR = fma(Xd, Xd, acc.RR);
         acc.UU = fma(Ud, Ud, acc.UU);

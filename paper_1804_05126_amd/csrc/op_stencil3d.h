@@ -114,7 +114,8 @@ struct Stencil3D {
     const __amdgpu_buffer_rsrc_t rsr = make_rsrc(r, nb);
     const __amdgpu_buffer_rsrc_t rsK = make_rsrc(kappa, nb);
     const __amdgpu_buffer_rsrc_t rsOut = make_rsrc(c.write_out ? Rout : nullptr, nb);
-    const __amdgpu_buffer_rsrc_t rsU = make_rsrc(c.store_u ? ubuf : nullptr, nb);
+    const bool store_u = uniform(c.store_u) != 0;   // full window only: no store otherwise
+    const __amdgpu_buffer_rsrc_t rsU = make_rsrc(store_u ? ubuf : nullptr, nb);
     __amdgpu_buffer_rsrc_t rsB[PB > 0 ? PB : 1];
 #pragma unroll
     for (int k = 0; k < PB; ++k) rsB[k] = make_rsrc(k < c.p ? B[k] : nullptr, nb);
@@ -269,7 +270,7 @@ struct Stencil3D {
           const uint32_t zo1 = (uint32_t)(wrap_index(zf - 1, nz) * plane);
           const uint32_t off1 = (zo1 + poff[0]) * (uint32_t)sizeof(T);
           buf_st(rsOut, valid ? off1 : kNoOffset, X);
-          buf_st(rsU, valid ? off1 : kNoOffset, U);
+          if (store_u) buf_st(rsU, valid ? off1 : kNoOffset, U);
           const double Xd = valid ? (double)X : 0.0, Ud = valid ? (double)U : 0.0;
           acc.RR = fma(Xd, Xd, acc.RR);
           acc.UU = fma(Ud, Ud, acc.UU);

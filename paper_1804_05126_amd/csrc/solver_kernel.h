@@ -50,10 +50,6 @@ __device__ inline void h_set(SmallState& S, const KParams& P, int i, int k, doub
   if (d >= 0 && d <= kWinMax) S.Hb[k][d] = v;   // the band kept in LDS
   P.H[i * kLdh + k] = v;                        // full copy in device memory
 }
-// H(i, k): the LDS band for windowed runs, device memory for a full window
-__device__ inline double h_any(const SmallState& S, const KParams& P, int i, int k) {
-  return S.C.q == 0 ? P.H[i * kLdh + k] : h_get(S, i, k);
-}
 __device__ inline double g_get(const SmallState& S, int i, int l) {   // |i - l| < kWinMax
   if (i < l) { const int t = i; i = l; l = t; }
   return S.Gw[i % kRingRows][l - (i - kWinMax + 1)];
@@ -289,12 +285,13 @@ __device__ __noinline__ void attempt_end(const KParams& P, SmallState& S, int j,
     const double tau = C.tau;
     // X = tau H~ (Eq. (37)) by columns, with its 1-norm
     double* A = P.expm;
+    const bool full = C.q == 0;   // full window: H in device memory, else the band in LDS
     double colmax = 0.0;
     for (int c = threadIdx.x; c < n16; c += kThreads) {
       double cs = 0.0;
       for (int r = 0; r < n16; ++r) {
         double v = 0.0;
-        if (r < j && c < j) v = tau * h_any(S, P, r + 1, c + 1);
+        if (r < j && c < j) v = tau * (full ? P.H[(r + 1) * kLdh + (c + 1)] : h_get(S, r + 1, c + 1));
         else if (c == j && r == 0) v = tau;
         A[r * kExpmLd + c] = v;
         cs += fabs(v);
@@ -482,9 +479,9 @@ __device__ inline int step_advance(SmallState& S, int k, int flo_next) {
 // vectors come from a separate phase first (epilogue_dots).
 __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, double* lds) {
   Ctrl& C = S.C;
-  const uint64_t tr0 = (uint64_t)wall_clock64();
+  const uint64_t tr0 = P.profile ? (uint64_t)wall_clock64() : 0;
   reduce_partials(P, S.red, lds, P.nwg);
-  if (threadIdx.x == 0) C.t_red += (uint64_t)wall_clock64() - tr0;
+  if (P.profile && threadIdx.x == 0) C.t_red += (uint64_t)wall_clock64() - tr0;
   if (C.q == 0 && C.kp > 1) {                 // full window: inner products first
     if (threadIdx.x == 0) C.phase = kPhaseDots;
     __syncthreads();
@@ -492,7 +489,7 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
     return;
   }
   if (threadIdx.x == 0) {
-    const uint64_t ts0 = (uint64_t)wall_clock64();
+    const uint64_t ts0 = P.profile ? (uint64_t)wall_clock64() : 0;
     const int k = C.kp;
     const int dlo = C.dlo;
     const int p = C.p;
@@ -548,14 +545,14 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
     }
     S.action = action;
     S.jj = k - 1;
-    C.t_ser += (uint64_t)wall_clock64() - ts0;
+    if (P.profile) C.t_ser += (uint64_t)wall_clock64() - ts0;
   }
   __syncthreads();
   const int action = S.action;
   if (action == 1 || action == 2) attempt_end(P, S, S.jj, action == 2, lds);
-  const uint64_t tp0 = (uint64_t)wall_clock64();
+  const uint64_t tp0 = P.profile ? (uint64_t)wall_clock64() : 0;
   publish(P, S);
-  if (threadIdx.x == 0) S.C.t_pub += (uint64_t)wall_clock64() - tp0;
+  if (P.profile && threadIdx.x == 0) S.C.t_pub += (uint64_t)wall_clock64() - tp0;
 }
 
 // Epilogue after the inner-product phase of a full-window step (q = 0): the
@@ -631,9 +628,9 @@ __device__ __noinline__ void epilogue_dots(const KParams& P, SmallState& S, doub
   }
   const int action = S.action;
   if (action == 1 || action == 2) attempt_end(P, S, S.jj, action == 2, lds);
-  const uint64_t tp0 = (uint64_t)wall_clock64();
+  const uint64_t tp0 = P.profile ? (uint64_t)wall_clock64() : 0;
   publish(P, S);
-  if (threadIdx.x == 0) S.C.t_pub += (uint64_t)wall_clock64() - tp0;
+  if (P.profile && threadIdx.x == 0) S.C.t_pub += (uint64_t)wall_clock64() - tp0;
 }
 
 // Epilogue after the gather: advance T_now (Alg. 1) and start the next substep.
