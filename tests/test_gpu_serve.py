@@ -139,3 +139,31 @@ def test_served_gangs_match_alone():
         assert rel(w, a) <= 2e-8, (pr.name, rel(w, a))
     announce(f"  gang sizes (workgroups): {sizes}")
     assert max(sizes) >= 64 and min(sizes) == 16
+
+
+def test_served_bitwise_alone_and_in_mix():
+    """On a gang of a given size a request computes the same bits whether it
+    runs alone on the server or among other requests (the reductions follow
+    the gang's workgroup order, not the timing)."""
+    import torch
+    import paper_1804_05126_amd as K
+    prs = _requests(12, seed=5301)
+    ins = _inputs(prs)
+    probe = [0, 3, 7]
+    alone = {}
+    srv = K.Server(pool_bytes=4 << 30, group_size=16)
+    try:
+        for i in probe:
+            pr, (op, vecs) = prs[i], ins[i]
+            t = srv.submit(op, pr.tau, vecs, tol=pr.tol)
+            res = _drain(srv, [t])
+            alone[i] = (res[t][0]["grid_blocks"], res[t][1])
+        announce(f"served bitwise: alone done, gangs {[alone[i][0] for i in probe]}")
+        tickets = [srv.submit(op, pr.tau, vecs, tol=pr.tol) for pr, (op, vecs) in zip(prs, ins)]
+        res = _drain(srv, tickets)
+    finally:
+        srv.close()
+    for i in probe:
+        st, w = res[tickets[i]]
+        assert st["grid_blocks"] == alone[i][0]
+        assert np.array_equal(w, alone[i][1]), (prs[i].name, rel(w, alone[i][1]))
