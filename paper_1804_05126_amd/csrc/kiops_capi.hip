@@ -357,6 +357,7 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   P.arrive_t = reinterpret_cast<uint64_t*>(ws + L.arrive_t);
   const char* ps = std::getenv("KIOPS_POLL_SLEEP");   // experiment override
   P.poll_sleep = ps ? std::max(0, std::min(64, std::atoi(ps))) : 1;
+  P.ranks = 1;
   const char* prof = std::getenv("KIOPS_PROFILE");
   P.profile = (prof && std::atoi(prof) > 0) ? 1 : 0;
   P.H = reinterpret_cast<double*>(ws + L.H);
@@ -423,6 +424,11 @@ kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, c
   hipError_t e = hipSuccess;
   // parameter block: KParams at +0, operator struct at +2048 (host staging buffer)
   static_assert(sizeof(KParams) <= 2048, "params block");
+  // workgroups per CU when the grid fills every CU evenly (the 7-point pass
+  // deals more items to the workgroups placed first on a CU)
+  P.ranks = (L.nwg % op->cus == 0 && L.nwg / op->cus <= 4) ? L.nwg / op->cus : 1;
+  const char* rk = std::getenv("KIOPS_RANKS");   // experiment override
+  if (rk) P.ranks = std::max(1, std::min(4, std::atoi(rk)));
   alignas(256) unsigned char host_block[4096];
   std::memset(host_block, 0, sizeof(host_block));
   std::memcpy(host_block, &P, sizeof(KParams));

@@ -134,7 +134,41 @@ struct Stencil3D {
     const int nloc = (vgrid() - band + nband - 1) / nband;
     const int i_lo = (int)((int64_t)nitems * band / nband);
     const int i_hi = (int)((int64_t)nitems * (band + 1) / nband);
-    for (int item = i_lo + vblock() / nband; item < i_hi; item += nloc) {
+    // Items are dealt in rounds, one per workgroup of the band in position
+    // order.  With R workgroups per CU the band's positions form R groups by
+    // dispatch order (position p is on the CU's (p R / nloc)-th workgroup);
+    // the first-dispatched workgroups are favoured by the SIMD arbitration and
+    // finish their items sooner (measured at 256^3, three per CU: 330, 380 and
+    // 427 us per pass), so the first group takes one item more and the last
+    // one less.  cnt(p) is non-increasing in p, so the workgroups of round j
+    // are the positions [0, size(j)) and position p takes item start(j) + p.
+    const int pos = vblock() / nband;
+    const int nbi = i_hi - i_lo;
+    const int base = nbi / nloc;
+    const int left = nbi - base * nloc;
+    const int R = (c.ranks >= 2 && nloc % c.ranks == 0 && base >= 2) ? c.ranks : 1;
+    const int gsz = nloc / R;
+    auto cnt = [&](int q) {
+      int v = base + (q < left ? 1 : 0);
+      if (R >= 2) {
+        const int g = q / gsz;
+        v += (g == 0 ? 1 : 0) - (g == R - 1 ? 1 : 0);
+      }
+      return v;
+    };
+    auto round_size = [&](int j) {
+      int lo = 0, hi = nloc;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cnt(mid) > j) lo = mid + 1;
+        else hi = mid;
+      }
+      return lo;
+    };
+    const int mine = cnt(pos);
+    int start = 0;
+    for (int j = 0; j < mine; start += round_size(j), ++j) {
+      const int item = i_lo + start + pos;
       const int tx = item % tiles_x;
       const int rest = item / tiles_x;
       const int x0 = tx * TX;

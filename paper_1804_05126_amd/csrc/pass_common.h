@@ -22,6 +22,7 @@ template <typename T>
 struct PassCtx {
   int kp, src, flo, dlo, ngd, first, write_out, p;
   int store_u;   // full window: also write U_kp (the inner products come from a later phase)
+  int ranks;     // workgroups per CU (KParams::ranks)
   T a;
   T bw[kLdh];
   T ybp[kPM];

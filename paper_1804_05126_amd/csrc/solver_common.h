@@ -101,6 +101,7 @@ struct KParams {
   int wg0;                     // served form: first workgroup of the gang running the solve
   unsigned epoch0;             // served form: grid-barrier epoch the solve starts from
   int poll_sleep;              // barrier polls: s_sleep(2) repeats between two reads of a flag
+  int ranks;                   // workgroups per CU of a grid that fills every CU evenly, else 1
   double T_end, tol;
   double elem_bytes;           // bytes per basis element (8 or 4)
   double coef_streams;         // per-cell coefficient arrays the operator reads

@@ -672,6 +672,7 @@ __device__ inline void load_pass_ctx(const KParams& P, PassCtx<T>& c) {
     c.p = C.p;
     c.a = (T)C.a;
     c.store_u = (C.q == 0);
+    c.ranks = P.ranks;
   }
   for (int i = threadIdx.x; i < kLdh; i += kThreads) c.bw[i] = (T)C.bw[i];
   if (threadIdx.x < kPM) {
