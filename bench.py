@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-substeps", type=int, default=2)
     ap.add_argument("--traffic-json", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--workload", choices=("adr2d", "diff3d", "batch", "serve"), default="adr2d",
+    ap.add_argument("--workload", choices=("adr2d", "diff3d", "batch", "serve", "small"), default="adr2d",
                     help="adr2d: the 2048^2 tau sweep (default); diff3d: the 256^3 variable-"
                          "coefficient solve; batch: 256 2-D problems in one launch vs a per-solve loop")
     ap.add_argument("--batch-count", type=int, default=256)
@@ -106,6 +106,8 @@ def main():
         return bench_batch(args, W, K, np, torch)
     if args.workload == "serve":
         return bench_serve(args, W, K, np, torch)
+    if args.workload == "small":
+        return bench_small(args, W, K, np, torch)
     taus = [float(t) for t in args.taus.split(",")] if args.taus else W.cfg2_tau_grid()
     side = args.side
     pr = W.cfg2(side, taus[0], q=args.q)       # operator and vectors shared by the sweep
@@ -260,6 +262,53 @@ def bench_diff3d(args, W, K, np, torch):
                      "avg_launch_ms": sum(ms) / len(ms)},
         "latency_ms": _lat(ms),
         "solve": {k: st[k] for k in ("matvecs", "substeps", "rejections", "m_last", "grid_blocks")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_small(args, W, K, np, torch):
+    """The 32^2 problem (N = 1024, p = 2, tau = 1e-2, tol 1e-8, q = 2): one solve
+    at a time (latency), 1000 solves back to back on one stream, and the same
+    1000 solves as one batched launch."""
+    pr = W.cfg1()
+    op = K.Operator.from_desc(pr.op)
+    vecs = [torch.as_tensor(v, device="cuda") for v in pr.vectors]
+    w = torch.empty(pr.n, dtype=torch.float64, device="cuda")
+    count = 1000
+    for _ in range(10):
+        K.phi_combination(op, pr.tau, vecs, tol=pr.tol, out=w)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(50):
+        s0 = time.perf_counter()
+        _, st, _ = K.phi_combination(op, pr.tau, vecs, tol=pr.tol, out=w)
+        lat.append((time.perf_counter() - s0) * 1e3)
+    t0 = time.perf_counter()
+    for _ in range(count):
+        K.phi_combination(op, pr.tau, vecs, tol=pr.tol, out=w)
+    torch.cuda.synchronize()
+    loop_s = time.perf_counter() - t0
+    outs = [torch.empty(pr.n, dtype=torch.float64, device="cuda") for _ in range(count)]
+    probs = [dict(op=op, tau=pr.tau, vectors=vecs, tol=pr.tol, m_init=pr.m_init, q=pr.q, out=o) for o in outs]
+    best, _ = K.batch_tune(probs, candidates=(8, 16, 32))
+    K.phi_batch(probs, group_size=best)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, stats, status, plan = K.phi_batch(probs, group_size=best)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t1
+    ok = all(x["status"] == 0 for x in stats) and all(torch.equal(o, outs[0]) for o in outs[1:])
+    out = {
+        "metric": METRIC, "value": count / batch_s, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": batch_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2-D ADR 32^2 (N=1024), p=2, tau=1e-2, tol 1e-8, q=2, m_init 10; 1000 solves",
+                   "seed": pr.seed, "group_size": best},
+        "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
+                     "note": "the 48 KiB working set stays in L2; per-step barriers and epilogues dominate"},
+        "single_solve_ms": _lat(lat), "matvecs_per_solve": st["matvecs"],
+        "back_to_back_solves_per_s": count / loop_s, "batched_solves_per_s": count / batch_s,
+        "batched_results_identical": ok,
     }
     print(json.dumps(out), flush=True)
 

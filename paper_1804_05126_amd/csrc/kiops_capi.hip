@@ -426,7 +426,7 @@ kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, c
   static_assert(sizeof(KParams) <= 2048, "params block");
   // workgroups per CU when the grid fills every CU evenly (the 7-point pass
   // deals more items to the workgroups placed first on a CU)
-  P.ranks = (L.nwg % op->cus == 0 && L.nwg / op->cus <= 4) ? L.nwg / op->cus : 1;
+  P.ranks = (uses_3d(op) && L.nwg % op->cus == 0 && L.nwg / op->cus <= 4) ? L.nwg / op->cus : 1;
   const char* rk = std::getenv("KIOPS_RANKS");   // experiment override
   if (rk) P.ranks = std::max(1, std::min(4, std::atoi(rk)));
   alignas(256) unsigned char host_block[4096];
