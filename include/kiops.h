@@ -102,6 +102,7 @@ typedef struct {
 
 #define KIOPS_M_MAX_LIMIT 128
 #define KIOPS_P_MAX 8
+#define KIOPS_MAX_TIMES 32   /* output times of one kiops_phi_combination_times call */
 
 /* Statistics of one solve.  m_last is the dimension to use as m_init of a
  * following, similar solve (Algorithm 1 returns it, Section 3.6). */
@@ -173,6 +174,23 @@ kiops_status kiops_set_workspace(kiops_operator* op, void* dev_ptr, size_t bytes
 kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const double* const* V,
                                    double tol, int m_init, int q, const kiops_options* opts,
                                    double* w, kiops_stats* stats);
+
+/* Several output times (Algorithm 1 with T = [T_1, ..., T_n] and Algorithm 3):
+ * one adaptive integration from 0 to T_n = T_end that, at every accepted
+ * substep containing output times T_k < T_now + tau, forms
+ * w_k = beta V F2(:, 1) with F2 = exp((T_k - T_now) H_j) from the same basis,
+ * then continues.  times: host array of n (1 <= n <= KIOPS_MAX_TIMES) strictly
+ * increasing positive values.  task: 2 (Task II) returns
+ * w_k = sum_i T_k^i phi_i(T_k A) b_i; 1 (Task I) returns the same scaled by
+ * (1 / T_k)^p (Algorithm 1, line 33; with only b_p nonzero this is
+ * phi_p(T_k A) b_p).  W: host array of n device pointers (N doubles each),
+ * distinct; W[n-1] also holds the running state (it may be V[0], in place);
+ * W[k], k < n-1, must not alias any V[i].  The small exponentials of the
+ * intermediate outputs count in stats->expms.  Errors as kiops_phi_combination
+ * (INVALID_ARG for bad times, task or outputs). */
+kiops_status kiops_phi_combination_times(kiops_operator* op, int n, const double* times, int task, int p,
+                                         const double* const* V, double tol, int m_init, int q,
+                                         const kiops_options* opts, double* const* W, kiops_stats* stats);
 
 /*
  * Batched form: many independent phi-combinations in one persistent launch.

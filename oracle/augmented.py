@@ -47,6 +47,21 @@ def phi_combination_dense(A: np.ndarray, tau: float, vectors: Sequence[np.ndarra
     return w if full else w[: A.shape[0]]
 
 
+def phi_combination_times(A: np.ndarray, times: Sequence[float], vectors: Sequence[np.ndarray],
+                          task: int = 2) -> List[np.ndarray]:
+    """Algorithm 1 with an array of output times T_1 < ... < T_n: the result at
+    T_k is the first N entries of exp(T_k A~) v (Theorem 1, Eq. (14)); for
+    Task I it is further multiplied by (1 / T_k)^p (Algorithm 1, the scaling
+    after the time loop), which leaves phi_p(T_k A) b_p when only b_p is
+    nonzero.  Dense, for small N."""
+    p = len(vectors) - 1
+    out = []
+    for t in times:
+        w = phi_combination_dense(A, t, vectors)
+        out.append(w * (1.0 / t) ** p if task == 1 else w)
+    return out
+
+
 def phi_combination_dense_desc(desc, tau: float, vectors: Sequence[np.ndarray]) -> np.ndarray:
     return phi_combination_dense(operators.dense(desc), tau, vectors)
 

@@ -169,6 +169,34 @@ def phi_combination(op: Operator, tau: float, vectors: Sequence, tol: float = 1e
     return w, st.as_dict(), status
 
 
+def phi_combination_times(op: Operator, times: Sequence[float], vectors: Sequence, task: int = 2,
+                          tol: float = 1e-8, m_init: int = 10, q: int = 2, m_min: int = 0, m_max: int = 0,
+                          max_substeps: int = 0, outs=None, check: bool = True):
+    """Several output times T_1 < ... < T_n in one integration (Algorithms 1 and 3):
+    outs[k] = sum_i T_k^i phi_i(T_k A) vectors[i] (task 2), times (1/T_k)^p for
+    task 1.  Returns (list of w, stats dict, status)."""
+    torch = _torch()
+    p = len(vectors) - 1
+    V = _vec_ptrs(vectors, op.n)
+    n = len(times)
+    if outs is None:
+        outs = [torch.empty(op.n, dtype=torch.float64, device="cuda") for _ in range(n)]
+    if len(outs) != n:
+        raise ValueError("one output per time")
+    for o in outs:
+        _require_cuda_f64(o, op.n, "outs")
+    op.ensure_workspace(op.workspace_bytes(p, q, m_min, m_max, max_substeps))
+    o = _lib.Options(m_min, m_max, max_substeps, 0)
+    st = _lib.Stats()
+    T = (C.c_double * n)(*[float(t) for t in times])
+    Wp = (C.c_void_p * n)(*[_ptr(x) for x in outs])
+    status = op._lib.kiops_phi_combination_times(op._h, n, T, int(task), p, V, float(tol), int(m_init), int(q),
+                                                 C.byref(o), Wp, C.byref(st))
+    if check:
+        _lib.check(status, "kiops_phi_combination_times")
+    return outs, st.as_dict(), status
+
+
 _batch_ws = {}
 
 

@@ -63,8 +63,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t params, ctrl, bar, arrive, arrive_t, H, G, Y, sinv, coefc, fullc, partials, dpart, expm, trace, slots,
-      ubuf, bcopy, coef, total;
+  size_t params, ctrl, bar, arrive, arrive_t, H, G, Y, sinv, coefc, fullc, partials, dpart, expm, trace, cgsave,
+      slots, ubuf, bcopy, coef, total;
   int nwg, ndot_stride, q;
 };
 
@@ -200,6 +200,7 @@ Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
   L.dpart = take(q == 0 ? sizeof(double) * (size_t)nwg * kDotFullStride : 0);
   L.expm = take(sizeof(double) * (size_t)kExpmSlots * kExpmSlot);
   L.trace = take(sizeof(double) * (size_t)kTraceMax * kTraceStride);
+  L.cgsave = take(sizeof(double) * kLdh);
   const size_t es = (size_t)elem_size(op);
   L.slots = take(es * (size_t)(m_max + 1) * (size_t)op->N);
   L.ubuf = take((q == 0 || op->d.kind == KIOPS_OP_CSR) ? es * (size_t)op->N : 0);
@@ -371,6 +372,11 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   P.partials = reinterpret_cast<double*>(ws + L.partials);
   P.expm = reinterpret_cast<double*>(ws + L.expm);
   P.trace = reinterpret_cast<double*>(ws + L.trace);
+  P.cgsave = reinterpret_cast<double*>(ws + L.cgsave);
+  P.ntimes = 1;           // one output, at T_end (Task II)
+  P.task1 = 0;
+  P.times[0] = tau;
+  P.wout[0] = w;
   return P;
 }
 
@@ -1080,6 +1086,52 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
   if (!op->ws || op->ws_bytes < L.total) return KIOPS_ERR_OUT_OF_MEMORY;
   KParams P = make_params(op, L, reinterpret_cast<char*>(op->ws), tau, p, V, tol, m_init, q, m_min, m_max,
                           max_sub, kModeSolve, w);
+  Ctrl hc{};
+  unsigned abort_flag = 0;
+  s = run_solve(op, L, P, p, V, &hc, &abort_flag);
+  if (s != KIOPS_OK) return s;
+  fill_stats(hc, nwg, (double)op->clock_hz, stats);
+  if (abort_flag) return KIOPS_ERR_DEVICE;
+  return (kiops_status)hc.status;
+}
+
+kiops_status kiops_phi_combination_times(kiops_operator* op, int n, const double* times, int task, int p,
+                                         const double* const* V, double tol, int m_init, int q,
+                                         const kiops_options* opts, double* const* W, kiops_stats* stats) {
+  if (!op || !times || !W || n < 1 || n > KIOPS_MAX_TIMES || (task != 1 && task != 2)) return KIOPS_ERR_INVALID_ARG;
+  if (!(tol > 0.0) || !std::isfinite(tol) || m_init < 1 || q < 0 || q > 8) return KIOPS_ERR_INVALID_ARG;
+  for (int k = 0; k < n; ++k) {
+    if (!(times[k] > 0.0) || !std::isfinite(times[k]) || (k > 0 && !(times[k] > times[k - 1])) || !W[k])
+      return KIOPS_ERR_INVALID_ARG;
+    for (int l = 0; l < k; ++l)
+      if (W[l] == W[k]) return KIOPS_ERR_INVALID_ARG;
+  }
+  double* w = W[n - 1];
+  kiops_status s = check_vectors(op, p, V, w);
+  if (s != KIOPS_OK) return s;
+  for (int k = 0; k + 1 < n; ++k)
+    for (int i = 0; i <= p; ++i)
+      if (W[k] == V[i]) return KIOPS_ERR_INVALID_ARG;
+  int m_min, m_max, max_sub;
+  resolve_options(op, opts, &m_min, &m_max, &max_sub);
+  if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max || m_min < 1) return KIOPS_ERR_INVALID_ARG;
+  if (q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
+  if (!kernel_for(op, p)) return KIOPS_ERR_UNSUPPORTED;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  int nwg = 0;
+  s = grid_size(op, p, &nwg);
+  if (s != KIOPS_OK) return s;
+  const double T_end = times[n - 1];
+  const Layout L = make_layout(op, p, q, m_max, nwg);
+  if (!op->ws || op->ws_bytes < L.total) return KIOPS_ERR_OUT_OF_MEMORY;
+  KParams P = make_params(op, L, reinterpret_cast<char*>(op->ws), T_end, p, V, tol, m_init, q, m_min, m_max,
+                          max_sub, kModeSolve, w);
+  P.ntimes = n;
+  P.task1 = task == 1 ? 1 : 0;
+  for (int k = 0; k < n; ++k) {
+    P.times[k] = times[k];
+    P.wout[k] = W[k];
+  }
   Ctrl hc{};
   unsigned abort_flag = 0;
   s = run_solve(op, L, P, p, V, &hc, &abort_flag);

@@ -22,6 +22,7 @@ constexpr int kPM = KIOPS_P_MAX;
 constexpr int kWinMax = 4;                          // windows q <= 4 use register accumulators
 constexpr int kTraceMax = 4096;
 constexpr int kTraceStride = 6;
+constexpr int kMaxTimes = KIOPS_MAX_TIMES;            // output times of one call
 constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
 
 enum Phase : int32_t { kPhasePass = 0, kPhaseGather = 1, kPhaseDone = 2, kPhaseDots = 3 };
@@ -69,6 +70,11 @@ struct Ctrl {
   // ---- statistics
   int32_t substeps, rejections, expms, breakdowns, attempts;
   uint32_t epoch_end;          // served form: grid-barrier epoch when the solve ended
+  // ---- several output times (Algorithms 1 and 3)
+  int32_t out_next;            // first output time not yet written (l)
+  int32_t pending;             // intermediate outputs of this substep still to gather
+  int32_t gather_to;           // output the next gather writes: -1 = the state w
+  int32_t pad2;
   int64_t matvecs;
   double last_omega, alg_bytes;
   double s_last;
@@ -126,6 +132,11 @@ struct KParams {
   double* partials;            // nwg x ndot_stride
   double* expm;                // small-exponential scratch
   double* trace;               // kTraceMax x kTraceStride
+  double* cgsave;              // several output times: the substep's own gather coefficients (kLdh)
+  int ntimes;                  // output times (1: only T_end)
+  int task1;                   // Task I: output l is scaled by (1 / T_l)^p (Algorithm 1)
+  double times[kMaxTimes];     // T_1 < ... < T_ntimes = T_end
+  double* wout[kMaxTimes];     // output l (wout[ntimes - 1] == w, the state)
 };
 
 // Work queue of one group of workgroups (batched and served launches).  The

@@ -272,6 +272,73 @@ __device__ inline double pass_bytes(const KParams& P, int kp, int flo) {
   return (reads + writes) * (double)P.N;
 }
 
+// Gather coefficients for output k inside an accepted substep (Algorithm 3):
+// F2 = exp(tau_k H(1:j, 1:j)) with tau_k = T_k - T_now, c_i = beta F2(i, 1) / s_i,
+// and for Task I the factor (1 / T_k)^p of Algorithm 1.  Whole workgroup.
+__device__ void output_coefs(const KParams& P, SmallState& S, int j, int k, double* lds) {
+  Ctrl& C = S.C;
+  const double tk = P.times[k] - C.T_now;
+  const int n16 = pad16(j);
+  double* A = P.expm;
+  const bool full = C.q == 0;
+  double colmax = 0.0;
+  for (int c = threadIdx.x; c < n16; c += kThreads) {
+    double cs = 0.0;
+    for (int r = 0; r < n16; ++r) {
+      const double v =
+          (r < j && c < j) ? tk * (full ? P.H[(r + 1) * kLdh + (c + 1)] : h_get(S, r + 1, c + 1)) : 0.0;
+      A[r * kExpmLd + c] = v;
+      cs += fabs(v);
+    }
+    colmax = cs > colmax ? cs : colmax;
+  }
+  const double eta = wg_max(colmax, lds);
+  const int slot = wg_expm(P.expm, j, eta, lds);
+  const double* F = P.expm + (size_t)slot * kExpmSlot;
+  const double scale = P.task1 ? pow(1.0 / P.times[k], (double)C.p) : 1.0;
+  for (int i = 1 + threadIdx.x; i <= j; i += kThreads) C.cg[i] = scale * C.beta * F[(i - 1) * kExpmLd] * S.sinv[i];
+  if (threadIdx.x == 0) C.expms += 1;
+  __syncthreads();
+}
+
+// Task I: the output at T_end is scaled by (1 / T_end)^p (Algorithm 1), folded
+// into the gather of the substep that reaches T_end.  Whole workgroup.
+__device__ void final_scale(const KParams& P, SmallState& S, int j) {
+  Ctrl& C = S.C;
+  const bool last = C.T_end - (C.T_now + C.tau) <= 8.0 * 2.220446049250313e-16 * C.T_end;
+  if (P.task1 && last) {
+    const double scale = pow(1.0 / C.T_end, (double)C.p);
+    for (int i = 1 + threadIdx.x; i <= j; i += kThreads) C.cg[i] *= scale;
+  }
+  __syncthreads();
+}
+
+// After the coefficients of an accepted substep are known: the output times
+// T_k (k >= l, not the last) with T_k < T_now + tau are written first, each
+// by its own gather (Algorithm 3); the substep's own gather, whose
+// coefficients are kept in device memory meanwhile, comes last.
+__device__ void begin_outputs(const KParams& P, SmallState& S, int j, double* lds) {
+  Ctrl& C = S.C;
+  if (threadIdx.x == 0) {
+    const double tnext = C.T_now + C.tau;
+    int n = 0;
+    for (int k = C.out_next; k < P.ntimes - 1; ++k)
+      if (P.times[k] < tnext) ++n;
+    C.pending = n;
+    C.gather_to = -1;
+  }
+  __syncthreads();
+  if (C.pending > 0) {
+    for (int i = threadIdx.x; i <= j; i += kThreads) P.cgsave[i] = C.cg[i];
+    __syncthreads();
+    output_coefs(P, S, j, C.out_next, lds);
+    if (threadIdx.x == 0) C.gather_to = C.out_next;
+    __syncthreads();
+  } else {
+    final_scale(P, S, j);
+  }
+}
+
 // The small exponential and the controller for an attempt with basis size j.
 // Whole workgroup.  Loops while the attempt is rejected at m_max (same basis,
 // smaller tau).
@@ -352,6 +419,7 @@ __device__ __noinline__ void attempt_end(const KParams& P, SmallState& S, int j,
       // gather coefficients c_i = beta F(i, 1) / s_{i-1}
       for (int i = 1 + threadIdx.x; i <= j; i += kThreads) C.cg[i] = C.beta * F[(i - 1) * kExpmLd] * S.sinv[i];
       __syncthreads();
+      begin_outputs(P, S, j, lds);
     }
     if (!S.again) break;
   }
@@ -382,6 +450,7 @@ __device__ __noinline__ void epilogue_setup(const KParams& P, SmallState& S, dou
     C.t_work = tw;
     C.t_last = tl;
     C.nu = nu; C.mu = mu;
+    C.gather_to = -1;
     C.T_now = 0.0; C.T_end = P.T_end; C.tau = P.T_end; C.tol = P.tol;
     C.p = P.p; C.q = P.q; C.m_min = P.m_min; C.m_max = P.m_max; C.max_substeps = P.max_substeps;
     int m = P.m_init < P.m_max ? P.m_init : P.m_max;   // Alg. 1: initial dimension
@@ -634,7 +703,28 @@ __device__ __noinline__ void epilogue_dots(const KParams& P, SmallState& S, doub
 }
 
 // Epilogue after the gather: advance T_now (Alg. 1) and start the next substep.
-__device__ __noinline__ void epilogue_gather(const KParams& P, SmallState& S) {
+__device__ __noinline__ void epilogue_gather(const KParams& P, SmallState& S, double* lds) {
+  if (S.C.gather_to >= 0) {   // an intermediate output was written (Algorithm 3)
+    if (threadIdx.x == 0) {
+      Ctrl& C = S.C;
+      C.alg_bytes += (8.0 + P.elem_bytes * (double)(C.jg - 1) + 8.0) * (double)P.N;
+      C.out_next = C.gather_to + 1;
+      C.pending -= 1;
+    }
+    __syncthreads();
+    if (S.C.pending > 0) {
+      output_coefs(P, S, S.C.jg, S.C.out_next, lds);
+      if (threadIdx.x == 0) S.C.gather_to = S.C.out_next;
+    } else {
+      for (int i = threadIdx.x; i <= S.C.jg; i += kThreads) S.C.cg[i] = P.cgsave[i];
+      __syncthreads();
+      if (threadIdx.x == 0) S.C.gather_to = -1;
+      final_scale(P, S, S.C.jg);
+    }
+    __syncthreads();
+    publish(P, S);
+    return;
+  }
   if (threadIdx.x == 0) {
     Ctrl& C = S.C;
     const double s = P.elem_bytes;
@@ -647,6 +737,7 @@ __device__ __noinline__ void epilogue_gather(const KParams& P, SmallState& S) {
     C.substeps += 1;
     if (C.T_now >= C.T_end) {
       C.phase = kPhaseDone;
+      C.out_next = P.ntimes;
     } else if (C.substeps >= C.max_substeps) {
       C.status = KIOPS_ERR_NOT_CONVERGED;
       C.phase = kPhaseDone;
@@ -725,6 +816,7 @@ template <typename T>
 __device__ inline void gather_phase(const KParams& P, const BasisPtrs<T>& bp, double* lds) {
   const Ctrl& C = *P.ctrl;
   const int jg = C.jg;
+  double* out = C.gather_to >= 0 ? P.wout[C.gather_to] : P.w;   // an output time, or the state
   for (int i = threadIdx.x; i <= jg; i += kThreads) lds[i] = C.cg[i];
   __syncthreads();
   const int64_t gt = (int64_t)vblock() * kThreads + threadIdx.x;
@@ -743,7 +835,7 @@ __device__ inline void gather_phase(const KParams& P, const BasisPtrs<T>& bp, do
       acc = fma(lds[i + 3], a3, acc);
     }
     for (; i <= jg; ++i) acc = fma(lds[i], (double)bp.get(i)[n], acc);
-    P.w[n] = acc;
+    out[n] = acc;
   }
   __syncthreads();
 }
@@ -881,7 +973,7 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
       grid_barrier(P, S, epoch, [&] { epilogue_dots(P, S, lds); });
     } else {
       gather_phase<T>(P, bp, lds);
-      grid_barrier(P, S, epoch, [&] { epilogue_gather(P, S); });
+      grid_barrier(P, S, epoch, [&] { epilogue_gather(P, S, lds); });
     }
   }
 }
