@@ -105,7 +105,10 @@ def main():
     if args.workload == "batch":
         return bench_batch(args, W, K, np, torch)
     if args.workload == "serve":
-        return bench_serve(args, W, K, np, torch)
+        # the library keeps the served launch switched off (an unexplained
+        # device fault in a served run); nothing of it is started here
+        print("bench.py: the served form is switched off in this library build", file=sys.stderr)
+        return 2
     if args.workload == "small":
         return bench_small(args, W, K, np, torch)
     taus = [float(t) for t in args.taus.split(",")] if args.taus else W.cfg2_tau_grid()
@@ -501,4 +504,4 @@ def _kernel_hash():
 
 
 if __name__ == "__main__":
-    main()
+    sys.exit(main() or 0)

@@ -743,6 +743,7 @@ kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B
 // ---------------------------------------------------------------- server
 
 constexpr int kServePB = 4;   // p-bucket of the served kernel (p <= 4)
+constexpr bool kServedEnabled = false;   // see kiops_server_create
 
 int serve_family(const kiops_operator* op) {
   const bool mixed = op->d.precision == KIOPS_MIXED;
@@ -1251,6 +1252,9 @@ kiops_status kiops_server_create(int group_size, int64_t points_per_workgroup, v
   if (st != KIOPS_OK) return st;
   const ServeLayout SL = serve_layout(gs, ng);
   if (workspace_bytes <= SL.pool) return KIOPS_ERR_OUT_OF_MEMORY;
+  // The served launch stays off until a device fault seen in a served run is
+  // explained; the code below is kept for that investigation.
+  if (!kServedEnabled) return KIOPS_ERR_UNSUPPORTED;
   kiops_server* s = new (std::nothrow) kiops_server();
   if (!s) return KIOPS_ERR_OUT_OF_MEMORY;
   s->run = reinterpret_cast<hipStream_t>(run_stream);
