@@ -60,6 +60,7 @@ __global__ void kiops_reset_kernel(Barrier* b, Ctrl* c, unsigned* arrive, int nw
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kGridExpmFrom = 96;   // padded basis size from which the exponential is spread over the grid
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
@@ -359,6 +360,10 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   const char* ps = std::getenv("KIOPS_POLL_SLEEP");   // experiment override
   P.poll_sleep = ps ? std::max(0, std::min(64, std::atoi(ps))) : 1;
   P.ranks = 1;
+  // the attempt's small exponential runs on the whole grid from this padded
+  // size on (one workgroup below it, where a product is cheaper than a barrier)
+  const char* ge = std::getenv("KIOPS_GRID_EXPM");   // experiment override (0: never)
+  P.expm_grid = ge ? std::max(0, std::atoi(ge)) : kGridExpmFrom;
   const char* prof = std::getenv("KIOPS_PROFILE");
   P.profile = (prof && std::atoi(prof) > 0) ? 1 : 0;
   P.H = reinterpret_cast<double*>(ws + L.H);

@@ -178,6 +178,34 @@ __device__ __forceinline__ void wg_power_sum(double* __restrict__ C, int n, int 
   __syncthreads();
 }
 
+// Degree index d (Taylor degree kTaylorDeg[d]) and number of squarings s for
+// a matrix with ||X||_1 = eta (criterion in the header comment).
+__device__ __forceinline__ void expm_plan(double eta, int& d, int& s) {
+  d = 5;
+  s = 0;
+  if (eta <= kTaylorTheta[5]) {
+    d = 0;
+    while (eta > kTaylorTheta[d]) ++d;
+  } else if (eta < 1e300) {
+    s = (int)ceil(log2(eta / kTaylorTheta[5]));
+    if (s > 1000) s = 1000;
+  }
+  // eta non-finite: no scaling; the result carries the NaN / Inf onward
+}
+
+// Coefficients of Paterson-Stockmeyer block k (one thread): cf[i] = c_{kb+i}
+// for i < b, cf[1] carrying alpha since slot 0 holds the unscaled X; the top
+// block also takes cf[b] = c_m (the coefficient of X^b).
+__device__ inline void expm_block_coefs(double* cf, int k, int b, double alpha, bool top) {
+  double c = 1.0;
+  for (int i = 1; i <= k * b; ++i) c /= (double)i;   // c_{kb}
+  for (int i = 0; i < b; ++i) {
+    cf[i] = (i == 1) ? c * alpha : c;
+    c /= (double)(k * b + i + 1);
+  }
+  cf[b] = top ? c : 0.0;                               // c_{(k+1)b} = c_m when top
+}
+
 // exp(X) for the n x n matrix X held in slot 0 of `scratch` (zero-padded to a
 // multiple of 16), eta = ||X||_1 (computed by the caller while it writes X).
 // Returns the slot (4 or 5) holding the result.  Slots 0..5 are used; slot 0
@@ -189,15 +217,8 @@ __device__ __forceinline__ int wg_expm(double* scratch, int n, double eta, doubl
   double* Z[2] = {scratch + 4 * kExpmSlot, scratch + 5 * kExpmSlot};
   double* cf = lds + 256;
 
-  int d = 5, s = 0;
-  if (eta <= kTaylorTheta[5]) {
-    d = 0;
-    while (eta > kTaylorTheta[d]) ++d;
-  } else if (eta < 1e300) {
-    s = (int)ceil(log2(eta / kTaylorTheta[5]));
-    if (s > 1000) s = 1000;
-  }
-  // eta non-finite: no scaling; the result carries the NaN / Inf onward
+  int d, s;
+  expm_plan(eta, d, s);
   const int m = kTaylorDeg[d], b = kTaylorBlk[d], q = m / b;
   const double alpha = ldexp(1.0, -s);
 
@@ -206,18 +227,8 @@ __device__ __forceinline__ int wg_expm(double* scratch, int n, double eta, doubl
   if (b >= 3) wg_gemm(X + 2 * kExpmSlot, X + kExpmSlot, X, n, n16, alpha, nullptr, nullptr, 0);
   if (b >= 4) wg_gemm(X + 3 * kExpmSlot, X + kExpmSlot, X + kExpmSlot, n, n16, 1.0, nullptr, nullptr, 0);
 
-  // coefficients of block k: cf[i] = c_{kb+i} for i < b (cf[1] carries alpha,
-  // since slot 0 holds the unscaled X); the top block also takes c_m X^b
   auto set_block = [&](int k, bool top) {
-    if (threadIdx.x == 0) {
-      double c = 1.0;
-      for (int i = 1; i <= k * b; ++i) c /= (double)i;   // c_{kb}
-      for (int i = 0; i < b; ++i) {
-        cf[i] = (i == 1) ? c * alpha : c;
-        c /= (double)(k * b + i + 1);
-      }
-      cf[b] = top ? c : 0.0;                               // c_{(k+1)b} = c_m when top
-    }
+    if (threadIdx.x == 0) expm_block_coefs(cf, k, b, alpha, top);
     __syncthreads();
   };
   set_block(q - 1, true);
@@ -233,6 +244,91 @@ __device__ __forceinline__ int wg_expm(double* scratch, int n, double eta, doubl
     cur ^= 1;
   }
   return 4 + cur;
+}
+
+// ---- The same exponential spread over the workgroups of a grid.
+//
+// The products of wg_expm run as stages separated by grid barriers:
+//   X^2;  then X^3 and X^4 together;  the top block's power sum (elementwise);
+//   the q - 1 block products;  the s squarings.
+// Each product tile is computed by one wave with the same strip code, in the
+// same order of operations, as in wg_expm, so the result is bitwise the same.
+
+// Number of stages for degree index d and s squarings.
+__device__ __forceinline__ int expm_stages(int d, int s) {
+  const int b = kTaylorBlk[d], q = kTaylorDeg[d] / b;
+  return (b >= 2 ? 1 : 0) + (b >= 3 ? 1 : 0) + 1 + (q - 1) + s;
+}
+
+// Slot holding the result after the last stage.
+__device__ __forceinline__ int expm_result_slot(int d, int s) {
+  const int q = kTaylorDeg[d] / kTaylorBlk[d];
+  return 4 + ((q - 1 + s) & 1);
+}
+
+// Stage st of exp(X) (X in slot 0 of `scratch`, n x n, degree index d,
+// s squarings, alpha = 2^-s) by workgroup wg of nwg.  The 16 x 16 tiles of a
+// stage's products are dealt to the waves of the grid: wave w of workgroup v
+// takes tiles v + nwg (w + 4 r), r = 0, 1, ...; the power-sum stage is dealt
+// element by element to all threads.  Every workgroup calls this (whole
+// workgroup); cf: 8 doubles of the workgroup's LDS.
+__device__ __noinline__ void grid_expm_stage(double* scratch, int n, int d, int s, double alpha, int st,
+                                             int wg, int nwg, double* cf) {
+  n = uniform(n);
+  d = uniform(d);
+  s = uniform(s);
+  alpha = uniform(alpha);
+  st = uniform(st);
+  wg = uniform(wg);
+  nwg = uniform(nwg);
+  const int n16 = pad16(n);
+  const int nt = n16 >> 4;
+  const int b = kTaylorBlk[d], q = kTaylorDeg[d] / b;
+  const int npow = (b >= 2 ? 1 : 0) + (b >= 3 ? 1 : 0);
+  double* X = uniform(scratch);
+  if (st == npow) {   // Z_{q-1}: the top block's power sum into slot 4
+    if (threadIdx.x == 0) expm_block_coefs(cf, q - 1, b, alpha, true);
+    __syncthreads();
+    double* Z = X + 4 * kExpmSlot;
+    for (int e = wg * kThreads + (int)threadIdx.x; e < n16 * n16; e += nwg * kThreads) {
+      const int r = e / n16, c = e - r * n16;
+      Z[r * kExpmLd + c] = power_sum(X, cf, b + 1, n, r, c);
+    }
+    return;
+  }
+  // one or two products C = alpha A B + (power sum of X); slots by stage
+  int ng = 1, c0 = 0, a0 = 0, b0 = 0, c1 = 0, a1 = 0, b1 = 0, nterms = 0;
+  double al0 = 1.0, al1 = 1.0;
+  if (st < npow) {
+    if (st == 0) {                       // X^2
+      c0 = 1; a0 = 0; b0 = 0; al0 = alpha * alpha;
+    } else {                             // X^3 = X^2 X, and X^4 = X^2 X^2
+      c0 = 2; a0 = 1; b0 = 0; al0 = alpha;
+      if (b >= 4) { ng = 2; c1 = 3; a1 = 1; b1 = 1; al1 = 1.0; }
+    }
+  } else if (st < npow + q) {            // block k: Z <- X^b Z + sum_{i<b} c_{kb+i} X^i
+    const int i = st - npow - 1;
+    const int cur = i & 1;
+    if (threadIdx.x == 0) expm_block_coefs(cf, q - 2 - i, b, alpha, false);
+    __syncthreads();
+    c0 = 4 + (cur ^ 1); a0 = b - 1; b0 = 4 + cur; nterms = b;
+  } else {                               // squaring i: Z <- Z Z
+    const int cur = (q - 1 + (st - npow - q)) & 1;
+    c0 = 4 + (cur ^ 1); a0 = 4 + cur; b0 = 4 + cur;
+  }
+  constexpr uint64_t kSlotBytes = (uint64_t)kExpmSlot * 8;
+  const __amdgpu_buffer_rsrc_t rP = make_rsrc(X, 4 * kSlotBytes);
+  const int tiles = nt * nt;
+  const int wv = uniform((int)(threadIdx.x >> 6));
+  for (int u = wg + nwg * wv; u < ng * tiles; u += 4 * nwg) {
+    const int g = u >= tiles ? 1 : 0;
+    const int t = u - g * tiles;
+    const int I = t / nt, J = t - I * nt;
+    const __amdgpu_buffer_rsrc_t rC = make_rsrc(X + (size_t)(g ? c1 : c0) * kExpmSlot, kSlotBytes);
+    const __amdgpu_buffer_rsrc_t rA = make_rsrc(X + (size_t)(g ? a1 : a0) * kExpmSlot, kSlotBytes);
+    const __amdgpu_buffer_rsrc_t rB = make_rsrc(X + (size_t)(g ? b1 : b0) * kExpmSlot, kSlotBytes);
+    gemm_strip<1>(rC, rA, rB, rP, n, n16, g ? al1 : al0, cf, nterms, I, J);
+  }
 }
 
 }  // namespace kiops

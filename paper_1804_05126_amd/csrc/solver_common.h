@@ -25,7 +25,7 @@ constexpr int kTraceStride = 6;
 constexpr int kMaxTimes = KIOPS_MAX_TIMES;            // output times of one call
 constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
 
-enum Phase : int32_t { kPhasePass = 0, kPhaseGather = 1, kPhaseDone = 2, kPhaseDots = 3 };
+enum Phase : int32_t { kPhasePass = 0, kPhaseGather = 1, kPhaseDone = 2, kPhaseDots = 3, kPhaseExpm = 4 };
 constexpr int kDotFullStride = 2 * kLdh;            // full-window inner products per workgroup
 enum Mode : int32_t { kModeSolve = 0, kModeBasis = 1 };
 // Served form: which solver body a request runs (p <= 4).
@@ -75,6 +75,13 @@ struct Ctrl {
   int32_t pending;             // intermediate outputs of this substep still to gather
   int32_t gather_to;           // output the next gather writes: -1 = the state w
   int32_t pad2;
+  // ---- the attempt's small exponential when it is spread over the grid
+  int32_t e_st, e_nst;         // next stage, number of stages
+  int32_t e_j, e_bd;           // basis size and breakdown flag of the attempt
+  int32_t e_d, e_s;            // Taylor degree index, squarings
+  int32_t e_round, pad3;       // exponentials of this attempt so far
+  double e_alpha;              // 2^-s
+  uint64_t e_t0;               // clock when the attempt's first exponential began
   int64_t matvecs;
   double last_omega, alg_bytes;
   double s_last;
@@ -108,6 +115,7 @@ struct KParams {
   unsigned epoch0;             // served form: grid-barrier epoch the solve starts from
   int poll_sleep;              // barrier polls: s_sleep(2) repeats between two reads of a flag
   int ranks;                   // workgroups per CU of a grid that fills every CU evenly, else 1
+  int expm_grid;               // padded size from which the small exponential runs on the whole grid (0: never)
   double T_end, tol;
   double elem_bytes;           // bytes per basis element (8 or 4)
   double coef_streams;         // per-cell coefficient arrays the operator reads

@@ -339,16 +339,80 @@ __device__ void begin_outputs(const KParams& P, SmallState& S, int j, double* ld
   }
 }
 
-// The small exponential and the controller for an attempt with basis size j.
-// Whole workgroup.  Loops while the attempt is rejected at m_max (same basis,
-// smaller tau).
-__device__ __noinline__ void attempt_end(const KParams& P, SmallState& S, int j, bool breakdown,
-                                         double* lds) {
+// Decision for an attempt with basis size j whose exponential F = exp(tau H~)
+// is in slot `slot` of the scratch: eps (Eq. (36)), Algorithm 4, and on
+// acceptance the gather coefficients.  Whole workgroup.  Returns true when
+// the attempt is to be repeated on the same basis with a smaller tau
+// (rejection at m_max).
+__device__ bool attempt_decide(const KParams& P, SmallState& S, int j, bool breakdown, int slot, double* lds) {
+  Ctrl& C = S.C;
+  const double* F = P.expm + (size_t)slot * kExpmSlot;
+  if (threadIdx.x == 0) {
+    const double tau = C.tau;
+    const double eps = breakdown ? 0.0 : C.beta * fabs(h_get(S, j + 1, j)) * fabs(F[(j - 1) * kExpmLd + j]);
+    CtrlIn ci;
+    ci.T_end = C.T_end; ci.tol = C.tol; ci.T_now = C.T_now; ci.tau = tau;
+    ci.m_min = C.m_min; ci.m_max = C.m_max; ci.m = C.m; ci.have_old = C.have_old;
+    ci.tau_old = C.tau_old; ci.eps_old = C.eps_old; ci.omega_old = C.omega_old;
+    ci.m_old = C.m_old; ci.reserved = 0;
+    const CtrlOut o = ctrl_decide(ci, j, eps, breakdown);
+    ctrl_record(ci, o, j, eps);
+    C.have_old = ci.have_old; C.tau_old = ci.tau_old; C.eps_old = ci.eps_old;
+    C.omega_old = ci.omega_old; C.m_old = ci.m_old;
+    C.expms += 1;
+    C.last_omega = o.omega;
+    if (C.attempts < kTraceMax) {
+      double* tr = P.trace + (size_t)C.attempts * kTraceStride;
+      tr[0] = (double)C.substeps; tr[1] = (double)j; tr[2] = tau;
+      tr[3] = o.omega; tr[4] = (double)o.accept; tr[5] = (double)o.branch;
+    }
+    C.attempts += 1;
+    int again = 0;
+    if (o.branch == kBranchNonFinite) {
+      C.status = KIOPS_ERR_NONFINITE;
+      C.phase = kPhaseDone;
+    } else if (o.accept) {
+      C.jg = j;
+      C.tau_new = o.tau_new;
+      C.m_new = o.m_new;
+      if (breakdown) C.breakdowns += 1;
+      C.phase = kPhaseGather;
+    } else {
+      C.rejections += 1;
+      if (j == C.m_max) {
+        C.tau = o.tau_new;
+        again = 1;
+        if (C.e_round >= 1000 || !(o.tau_new > 0.0)) {   // step size collapsed: give up
+          C.status = KIOPS_ERR_NOT_CONVERGED;
+          C.phase = kPhaseDone;
+          again = 0;
+        }
+      } else {
+        C.m = o.m_new;
+        C.phase = kPhasePass;
+      }
+    }
+    C.e_round += 1;
+    S.again = again;
+  }
+  __syncthreads();
+  if (C.phase == kPhaseGather) {
+    // gather coefficients c_i = beta F(i, 1) / s_{i-1}
+    for (int i = 1 + threadIdx.x; i <= j; i += kThreads) C.cg[i] = C.beta * F[(i - 1) * kExpmLd] * S.sinv[i];
+    __syncthreads();
+    begin_outputs(P, S, j, lds);
+  }
+  return S.again != 0;
+}
+
+// Exponentials of the attempt (X = tau H~ of Eq. (37)) and their decisions,
+// until the attempt is decided or an exponential is handed to the whole grid
+// (phase kPhaseExpm, continued by epilogue_expm).  Whole workgroup.
+__device__ void attempt_run(const KParams& P, SmallState& S, int j, bool breakdown, double* lds) {
   Ctrl& C = S.C;
   const int n = j + 1;
   const int n16 = pad16(n);
-  const uint64_t te0 = (uint64_t)wall_clock64();
-  for (int round = 0;; ++round) {
+  for (;;) {
     const double tau = C.tau;
     // X = tau H~ (Eq. (37)) by columns, with its 1-norm
     double* A = P.expm;
@@ -366,64 +430,64 @@ __device__ __noinline__ void attempt_end(const KParams& P, SmallState& S, int j,
       colmax = cs > colmax ? cs : colmax;
     }
     const double eta = wg_max(colmax, lds);
+    if (P.expm_grid > 0 && P.nwg > 1 && n16 >= P.expm_grid) {
+      if (threadIdx.x == 0) {
+        int d, s;
+        expm_plan(eta, d, s);
+        C.e_j = j;
+        C.e_bd = breakdown ? 1 : 0;
+        C.e_d = d;
+        C.e_s = s;
+        C.e_alpha = ldexp(1.0, -s);
+        C.e_st = 0;
+        C.e_nst = expm_stages(d, s);
+        C.phase = kPhaseExpm;
+      }
+      __syncthreads();
+      return;
+    }
     const int slot = wg_expm(P.expm, n, eta, lds);
-    const double* F = P.expm + (size_t)slot * kExpmSlot;
-    if (threadIdx.x == 0) {
-      const double eps = breakdown ? 0.0 : C.beta * fabs(h_get(S, j + 1, j)) * fabs(F[(j - 1) * kExpmLd + j]);
-      CtrlIn ci;
-      ci.T_end = C.T_end; ci.tol = C.tol; ci.T_now = C.T_now; ci.tau = tau;
-      ci.m_min = C.m_min; ci.m_max = C.m_max; ci.m = C.m; ci.have_old = C.have_old;
-      ci.tau_old = C.tau_old; ci.eps_old = C.eps_old; ci.omega_old = C.omega_old;
-      ci.m_old = C.m_old; ci.reserved = 0;
-      const CtrlOut o = ctrl_decide(ci, j, eps, breakdown);
-      ctrl_record(ci, o, j, eps);
-      C.have_old = ci.have_old; C.tau_old = ci.tau_old; C.eps_old = ci.eps_old;
-      C.omega_old = ci.omega_old; C.m_old = ci.m_old;
-      C.expms += 1;
-      C.last_omega = o.omega;
-      if (C.attempts < kTraceMax) {
-        double* tr = P.trace + (size_t)C.attempts * kTraceStride;
-        tr[0] = (double)C.substeps; tr[1] = (double)j; tr[2] = tau;
-        tr[3] = o.omega; tr[4] = (double)o.accept; tr[5] = (double)o.branch;
-      }
-      C.attempts += 1;
-      int again = 0;
-      if (o.branch == kBranchNonFinite) {
-        C.status = KIOPS_ERR_NONFINITE;
-        C.phase = kPhaseDone;
-      } else if (o.accept) {
-        C.jg = j;
-        C.tau_new = o.tau_new;
-        C.m_new = o.m_new;
-        if (breakdown) C.breakdowns += 1;
-        C.phase = kPhaseGather;
-      } else {
-        C.rejections += 1;
-        if (j == C.m_max) {
-          C.tau = o.tau_new;
-          again = 1;
-          if (round >= 1000 || !(o.tau_new > 0.0)) {   // step size collapsed: give up
-            C.status = KIOPS_ERR_NOT_CONVERGED;
-            C.phase = kPhaseDone;
-            again = 0;
-          }
-        } else {
-          C.m = o.m_new;
-          C.phase = kPhasePass;
-        }
-      }
-      S.again = again;
+    if (!attempt_decide(P, S, j, breakdown, slot, lds)) break;
+  }
+  if (threadIdx.x == 0) C.t_expm += (uint64_t)wall_clock64() - C.e_t0;
+}
+
+// The small exponential and the controller for an attempt with basis size j.
+// Whole workgroup.  Repeats while the attempt is rejected at m_max (same
+// basis, smaller tau).
+__device__ __noinline__ void attempt_end(const KParams& P, SmallState& S, int j, bool breakdown,
+                                         double* lds) {
+  if (threadIdx.x == 0) {
+    S.C.e_round = 0;
+    S.C.e_t0 = (uint64_t)wall_clock64();
+  }
+  __syncthreads();
+  attempt_run(P, S, j, breakdown, lds);
+}
+
+// Epilogue after a stage of a grid-wide small exponential: the next stage, or
+// the attempt's decision once the exponential is complete.
+__device__ __noinline__ void epilogue_expm(const KParams& P, SmallState& S, double* lds) {
+  Ctrl& C = S.C;
+  if (threadIdx.x == 0) C.e_st += 1;
+  __syncthreads();
+  if (C.e_st >= C.e_nst) {
+    const int j = C.e_j;
+    const bool breakdown = C.e_bd != 0;
+    if (attempt_decide(P, S, j, breakdown, expm_result_slot(C.e_d, C.e_s), lds)) {
+      attempt_run(P, S, j, breakdown, lds);
+    } else if (threadIdx.x == 0) {
+      C.t_expm += (uint64_t)wall_clock64() - C.e_t0;
     }
     __syncthreads();
-    if (C.phase == kPhaseGather) {
-      // gather coefficients c_i = beta F(i, 1) / s_{i-1}
-      for (int i = 1 + threadIdx.x; i <= j; i += kThreads) C.cg[i] = C.beta * F[(i - 1) * kExpmLd] * S.sinv[i];
-      __syncthreads();
-      begin_outputs(P, S, j, lds);
-    }
-    if (!S.again) break;
   }
-  if (threadIdx.x == 0) C.t_expm += (uint64_t)wall_clock64() - te0;
+  publish(P, S);
+}
+
+// Stage of a grid-wide small exponential (every workgroup).
+__device__ inline void expm_phase(const KParams& P, double* lds) {
+  const Ctrl& C = *P.ctrl;
+  grid_expm_stage(P.expm, C.e_j + 1, C.e_d, C.e_s, C.e_alpha, C.e_st, vblock(), P.nwg, lds);
 }
 
 // Epilogue after the setup phase.
@@ -971,6 +1035,9 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
     } else if (phase == kPhaseDots) {
       dots_phase<T>(P, bp, lds);
       grid_barrier(P, S, epoch, [&] { epilogue_dots(P, S, lds); });
+    } else if (phase == kPhaseExpm) {
+      expm_phase(P, lds);
+      grid_barrier(P, S, epoch, [&] { epilogue_expm(P, S, lds); });
     } else {
       gather_phase<T>(P, bp, lds);
       grid_barrier(P, S, epoch, [&] { epilogue_gather(P, S, lds); });
