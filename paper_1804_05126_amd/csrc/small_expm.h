@@ -251,8 +251,8 @@ __device__ __forceinline__ int wg_expm(double* scratch, int n, double eta, doubl
 // The products of wg_expm run as stages separated by grid barriers:
 //   X^2;  then X^3 and X^4 together;  the top block's power sum (elementwise);
 //   the q - 1 block products;  the s squarings.
-// Each product tile is computed by one wave with the same strip code, in the
-// same order of operations, as in wg_expm, so the result is bitwise the same.
+// Each product tile is computed by one wave with the same products in the
+// same order as in wg_expm, so the result is bitwise the same.
 
 // Number of stages for degree index d and s squarings.
 __device__ __forceinline__ int expm_stages(int d, int s) {
@@ -264,6 +264,62 @@ __device__ __forceinline__ int expm_stages(int d, int s) {
 __device__ __forceinline__ int expm_result_slot(int d, int s) {
   const int q = kTaylorDeg[d] / kTaylorBlk[d];
   return 4 + ((q - 1 + s) & 1);
+}
+
+// One 16 x 16 tile (I, J) of C = alpha A B + (power sum) by one wave, with
+// the same products in the same order as gemm_strip<1>, but with the operand
+// loads issued kB 8-deep slices at a time, one batch ahead: the operands
+// were written by other workgroups just before, so each load is a full
+// memory round trip, and a one-slice lookahead would pay one per slice.
+template <int kB>
+__device__ __forceinline__ void gemm_tile_deep(__amdgpu_buffer_rsrc_t rC, __amdgpu_buffer_rsrc_t rA,
+                                               __amdgpu_buffer_rsrc_t rB, __amdgpu_buffer_rsrc_t rP, int n,
+                                               int n16, double alpha, const double* cf, int nterms, int I,
+                                               int J) {
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, g = lane >> 4;
+  constexpr uint32_t kRow = kExpmLd * 8;   // bytes per row
+  const uint32_t oA = (uint32_t)((I * 16 + r16) * kExpmLd + 2 * g) * 8u;
+  const uint32_t oB = (uint32_t)(2 * g * kExpmLd + J * 16 + r16) * 8u;
+  const int nsl = n16 >> 3;                // 8-deep slices
+  kiops_f64x4 acc = kiops_f64x4{0.0, 0.0, 0.0, 0.0};
+  double xa0[kB], xa1[kB], xb0[kB], xb1[kB], ya0[kB], ya1[kB], yb0[kB], yb1[kB];
+  auto load = [&](int s0, double* a0, double* a1, double* b0, double* b1) {
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      if (s0 + i < nsl) {
+        const uint32_t k = (uint32_t)(s0 + i) * 8u;
+        buf_ld2(rA, oA + k * 8u, a0[i], a1[i]);
+        b0[i] = buf_ld(rB, oB + k * kRow, 0.0);
+        b1[i] = buf_ld(rB, oB + k * kRow + kRow, 0.0);
+      }
+    }
+  };
+  auto mma = [&](int s0, const double* a0, const double* a1, const double* b0, const double* b1) {
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      if (s0 + i < nsl) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[i], b0[i], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[i], b1[i], acc, 0, 0, 0);
+      }
+    }
+  };
+  load(0, xa0, xa1, xb0, xb1);
+  for (int s0 = 0; s0 < nsl; s0 += 2 * kB) {
+    load(s0 + kB, ya0, ya1, yb0, yb1);
+    mma(s0, xa0, xa1, xb0, xb1);
+    load(s0 + 2 * kB, xa0, xa1, xb0, xb1);
+    mma(s0 + kB, ya0, ya1, yb0, yb1);
+  }
+  const int col = J * 16 + r16;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = I * 16 + g + 4 * i;
+    const uint32_t o = (uint32_t)(row * kExpmLd + col);
+    double v = (nterms > 0 && row == col && row < n) ? cf[0] : 0.0;
+    for (int k = 1; k < nterms; ++k) v = fma(cf[k], buf_ld(rP, (o + (uint32_t)(k - 1) * kExpmSlot) * 8u, 0.0), v);
+    buf_st(rC, o * 8u, fma(alpha, acc[i], v));
+  }
 }
 
 // Stage st of exp(X) (X in slot 0 of `scratch`, n x n, degree index d,
@@ -327,7 +383,7 @@ __device__ __noinline__ void grid_expm_stage(double* scratch, int n, int d, int 
     const __amdgpu_buffer_rsrc_t rC = make_rsrc(X + (size_t)(g ? c1 : c0) * kExpmSlot, kSlotBytes);
     const __amdgpu_buffer_rsrc_t rA = make_rsrc(X + (size_t)(g ? a1 : a0) * kExpmSlot, kSlotBytes);
     const __amdgpu_buffer_rsrc_t rB = make_rsrc(X + (size_t)(g ? b1 : b0) * kExpmSlot, kSlotBytes);
-    gemm_strip<1>(rC, rA, rB, rP, n, n16, g ? al1 : al0, cf, nterms, I, J);
+    gemm_tile_deep<6>(rC, rA, rB, rP, n, n16, g ? al1 : al0, cf, nterms, I, J);
   }
 }
 

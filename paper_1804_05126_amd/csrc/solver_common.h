@@ -76,7 +76,7 @@ struct Ctrl {
   int32_t gather_to;           // output the next gather writes: -1 = the state w
   int32_t pad2;
   // ---- the attempt's small exponential when it is spread over the grid
-  int32_t e_st, e_nst;         // next stage, number of stages
+  int32_t e_nst, pad4;         // number of stages
   int32_t e_j, e_bd;           // basis size and breakdown flag of the attempt
   int32_t e_d, e_s;            // Taylor degree index, squarings
   int32_t e_round, pad3;       // exponentials of this attempt so far

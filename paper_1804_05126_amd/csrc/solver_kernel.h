@@ -186,6 +186,49 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
   __syncthreads();
 }
 
+// Barrier among the first nw workgroups of the grid only (the others are not
+// waiting on it): the same arrival slots, release word and epoch sequence as
+// grid_barrier, with no epilogue.  The workgroups left out add the number of
+// these barriers to their epoch before the next grid barrier, so that every
+// epoch agrees there.
+__device__ inline void sub_barrier(const KParams& P, SmallState& S, unsigned& epoch, int nw) {
+  Barrier* b = P.bar;
+  ++epoch;
+  __syncthreads();
+  if (vblock() != 0) {
+    if (threadIdx.x == 0) {
+      __threadfence();
+      __hip_atomic_store(&P.arrive[vblock()], epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
+      const uint64_t t0 = (uint64_t)wall_clock64();
+      for (unsigned spins = 1;; ++spins) {
+        if (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) break;
+        for (int z = 0; z < P.poll_sleep; ++z) __builtin_amdgcn_s_sleep(2);
+        if ((spins & 63u) == 0 && spin_expired(b, t0, P.spin_limit)) break;
+      }
+      __threadfence();
+    }
+    __syncthreads();
+    return;
+  }
+  const uint64_t t0 = (uint64_t)wall_clock64();
+  for (unsigned spins = 1;; ++spins) {
+    int ok = 1;
+    for (unsigned w = 1 + threadIdx.x; w < (unsigned)nw; w += kThreads)
+      ok &= (__hip_atomic_load(&P.arrive[w], __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) ? 1 : 0;
+    if (__syncthreads_and(ok)) break;
+    for (int z = 0; z < P.poll_sleep; ++z) __builtin_amdgcn_s_sleep(2);
+    if ((spins & 15u) == 0) {
+      if (threadIdx.x == 0) S.expired = spin_expired(b, t0, P.spin_limit) ? 1 : 0;
+      __syncthreads();
+      if (S.expired) break;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
+  __syncthreads();
+}
+
 __device__ inline bool aborted(const KParams& P) {
   return __hip_atomic_load(&P.bar->abort, __ATOMIC_RELAXED, KIOPS_AGENT) != 0;
 }
@@ -439,7 +482,6 @@ __device__ void attempt_run(const KParams& P, SmallState& S, int j, bool breakdo
         C.e_d = d;
         C.e_s = s;
         C.e_alpha = ldexp(1.0, -s);
-        C.e_st = 0;
         C.e_nst = expm_stages(d, s);
         C.phase = kPhaseExpm;
       }
@@ -465,29 +507,48 @@ __device__ __noinline__ void attempt_end(const KParams& P, SmallState& S, int j,
   attempt_run(P, S, j, breakdown, lds);
 }
 
-// Epilogue after a stage of a grid-wide small exponential: the next stage, or
-// the attempt's decision once the exponential is complete.
+// Epilogue after a grid-wide small exponential: the attempt's decision, and
+// the next exponential if the attempt is repeated with a smaller tau.
 __device__ __noinline__ void epilogue_expm(const KParams& P, SmallState& S, double* lds) {
   Ctrl& C = S.C;
-  if (threadIdx.x == 0) C.e_st += 1;
-  __syncthreads();
-  if (C.e_st >= C.e_nst) {
-    const int j = C.e_j;
-    const bool breakdown = C.e_bd != 0;
-    if (attempt_decide(P, S, j, breakdown, expm_result_slot(C.e_d, C.e_s), lds)) {
-      attempt_run(P, S, j, breakdown, lds);
-    } else if (threadIdx.x == 0) {
-      C.t_expm += (uint64_t)wall_clock64() - C.e_t0;
-    }
-    __syncthreads();
+  const int j = C.e_j;
+  const bool breakdown = C.e_bd != 0;
+  if (attempt_decide(P, S, j, breakdown, expm_result_slot(C.e_d, C.e_s), lds)) {
+    attempt_run(P, S, j, breakdown, lds);
+  } else if (threadIdx.x == 0) {
+    C.t_expm += (uint64_t)wall_clock64() - C.e_t0;
   }
+  __syncthreads();
   publish(P, S);
 }
 
-// Stage of a grid-wide small exponential (every workgroup).
-__device__ inline void expm_phase(const KParams& P, double* lds) {
+// Workgroups that compute a grid-wide exponential of padded size n16: one
+// tile of a product per wave (the stage of X^3 and X^4 has two).
+__device__ __forceinline__ int expm_participants(int n16, int nwg) {
+  const int nt = n16 >> 4;
+  const int want = (nt * nt + 3) / 4;
+  return want < nwg ? want : nwg;
+}
+
+// A grid-wide small exponential: its stages run on the first workgroups of the
+// grid, separated by barriers among them; the others go straight to the grid
+// barrier that ends the phase.
+template <class F>
+__device__ inline void expm_phase(const KParams& P, SmallState& S, unsigned& epoch, double* lds, F&& epi) {
   const Ctrl& C = *P.ctrl;
-  grid_expm_stage(P.expm, C.e_j + 1, C.e_d, C.e_s, C.e_alpha, C.e_st, vblock(), P.nwg, lds);
+  const int n = uniform(C.e_j) + 1;
+  const int d = uniform(C.e_d), s = uniform(C.e_s), nst = uniform(C.e_nst);
+  const double alpha = uniform(C.e_alpha);
+  const int npart = expm_participants(pad16(n), P.nwg);
+  if (vblock() < npart) {
+    for (int st = 0; st < nst; ++st) {
+      grid_expm_stage(P.expm, n, d, s, alpha, st, vblock(), npart, lds);
+      if (st + 1 < nst) sub_barrier(P, S, epoch, npart);
+    }
+  } else {
+    epoch += (unsigned)(nst - 1);
+  }
+  grid_barrier(P, S, epoch, epi);
 }
 
 // Epilogue after the setup phase.
@@ -1036,8 +1097,7 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
       dots_phase<T>(P, bp, lds);
       grid_barrier(P, S, epoch, [&] { epilogue_dots(P, S, lds); });
     } else if (phase == kPhaseExpm) {
-      expm_phase(P, lds);
-      grid_barrier(P, S, epoch, [&] { epilogue_expm(P, S, lds); });
+      expm_phase(P, S, epoch, lds, [&] { epilogue_expm(P, S, lds); });
     } else {
       gather_phase<T>(P, bp, lds);
       grid_barrier(P, S, epoch, [&] { epilogue_gather(P, S, lds); });
