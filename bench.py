@@ -504,4 +504,6 @@ def _kernel_hash():
 
 
 if __name__ == "__main__":
-    sys.exit(main() or 0)
+    _rc = main()
+    if _rc:   # a normal run ends by falling off the end (no SystemExit)
+        sys.exit(_rc)
