@@ -875,7 +875,7 @@ __device__ __noinline__ void epilogue_gather(const KParams& P, SmallState& S, do
 }
 
 template <typename T>
-__device__ inline void load_pass_ctx(const KParams& P, PassCtx<T>& c) {
+__device__ inline void load_pass_ctx_nosync(const KParams& P, PassCtx<T>& c) {
   const Ctrl& C = *P.ctrl;
   if (threadIdx.x == 0) {
     c.kp = C.kp;
@@ -895,7 +895,6 @@ __device__ inline void load_pass_ctx(const KParams& P, PassCtx<T>& c) {
     c.ybp[threadIdx.x] = (T)C.yb_prev[threadIdx.x];
     c.ybc[threadIdx.x] = (T)C.yb_cur[threadIdx.x];
   }
-  __syncthreads();
 }
 
 // Write the per-workgroup partial inner products of a pass (fixed slots kDot*).
@@ -1073,14 +1072,19 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
   grid_barrier(P, S, epoch, [&] { epilogue_setup(P, S, lds); });
 
   for (;;) {
-    if (aborted(P)) break;
-    if (threadIdx.x == 0) s_phase = __hip_atomic_load(&P.ctrl->phase, __ATOMIC_RELAXED, KIOPS_AGENT);
+    // the abort flag, the next phase and (in case it is a pass) the pass
+    // coefficients are read in one round of loads
+    if (threadIdx.x == 0) {
+      const unsigned ab = __hip_atomic_load(&P.bar->abort, __ATOMIC_RELAXED, KIOPS_AGENT);
+      const int ph = __hip_atomic_load(&P.ctrl->phase, __ATOMIC_RELAXED, KIOPS_AGENT);
+      s_phase = ab ? (int)kPhaseDone : ph;
+    }
+    load_pass_ctx_nosync<T>(P, pctx);
     __syncthreads();
     const int phase = s_phase;
     __syncthreads();
     if (phase == kPhaseDone) break;
     if (phase == kPhasePass) {
-      load_pass_ctx<T>(P, pctx);
       DotAcc acc;
       acc.zero();
       T* Rout = bp.get_mut(pctx.kp);
