@@ -91,7 +91,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(instances shard by GPU with no exchange; see the design notes).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -107,7 +107,7 @@ def main():
     if args.workload == "serve":
         # the library keeps the served launch switched off (an unexplained
         # device fault in a served run); nothing of it is started here
-        print("bench.py: the served form is switched off in this library build", file=sys.stderr)
+        print("bench.py: the served form is switched off in this library", file=sys.stderr)
         return 2
     if args.workload == "small":
         return bench_small(args, W, K, np, torch)

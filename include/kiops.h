@@ -41,7 +41,7 @@ typedef enum {
   KIOPS_ERR_NONFINITE = 4,       /* NaN/Inf met in a norm, an inner product or the estimate */
   KIOPS_ERR_NOT_CONVERGED = 5,   /* substep limit reached; w holds the state at stats.t_reached */
   KIOPS_ERR_BUDGET = 6,          /* request larger than the caller's memory budget (serving) */
-  KIOPS_ERR_UNSUPPORTED = 7      /* valid request this build does not handle */
+  KIOPS_ERR_UNSUPPORTED = 7      /* valid request the library does not handle */
 } kiops_status;
 
 typedef enum {
