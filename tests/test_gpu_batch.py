@@ -95,3 +95,26 @@ def test_batch_tune_picks_a_candidate():
     announce("autotune over group sizes 8, 16")
     best, ms = K.batch_tune(_problems(prs), candidates=(8, 16))
     assert best in (8, 16) and ms > 0
+
+
+def test_full_batch_workload_matches_single_solves_and_oracle():
+    """The batched workload at its full size, in the configuration bench.py
+    times (256 problems, group size autotuned there, 16 here): every result
+    agrees with the same problem solved alone, and the three smallest agree
+    with the oracle's full-Arnoldi route."""
+    import paper_1804_05126_amd as K
+    from oracle.arnoldi import phi_combination_arnoldi
+    prs = W.cfg4()
+    probs = _problems(prs)
+    announce(f"full batch: {len(prs)} problems, {sum(pr.n for pr in prs)} points")
+    ws, stats, status, plan = K.phi_batch(probs, group_size=16)
+    assert status == 0
+    assert all(st["status"] == 0 for st in stats)
+    for pr, pb, w in zip(prs, probs, ws):
+        single, st, s1 = K.phi_combination(pb["op"], pr.tau, pb["vectors"], tol=pr.tol)
+        assert s1 == 0
+        assert rel(w.cpu().numpy(), single.cpu().numpy()) <= 2e-8, pr.name
+    for i in sorted(range(len(prs)), key=lambda i: prs[i].n)[:3]:
+        pr = prs[i]
+        ref = phi_combination_arnoldi(operators.make_apply(pr.op), pr.tau, pr.vectors, tol_o=1e-12)
+        assert rel(ws[i].cpu().numpy(), ref) <= 1e-8, (pr.name, rel(ws[i].cpu().numpy(), ref))
