@@ -202,19 +202,40 @@ def main():
         "matvecs_per_s": sum(st["matvecs"] for *_, st in records) / wall,
         "per_tau": per_tau,
     }
-    if args.calibrate_copy > 0:
-        nbytes = args.calibrate_copy << 20
-        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        torch.mul(src, 1.0, out=dst)      # elementwise kernel: reads and writes nbytes
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = nbytes
-        del src, dst
+    _calibrate_copy(args, torch, out)
     if not args.no_cpu_baseline:
         sample = W.cfg2(side, taus[0], q=args.q)
         out["cpu_baseline"] = cpu_baseline(sample, taus, args.cpu_sample_substeps)
     print(json.dumps(out), flush=True)
+
+
+def _calibrate_copy(args, torch, out):
+    """One plain elementwise copy of a known size after the timed region, so
+    that hardware byte counters can be scaled by what they read for it."""
+    if args.calibrate_copy <= 0:
+        return
+    nbytes = args.calibrate_copy << 20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.mul(src, 1.0, out=dst)      # elementwise kernel: reads and writes nbytes
+    torch.cuda.synchronize()
+    out["copy_calibration_bytes"] = nbytes
+    del src, dst
+
+
+def _traffic(path, key):
+    """HBM bytes per launch from a counter summary under profiles/, if it was
+    taken for this workload key and the current kernel sources."""
+    if not os.path.exists(path):
+        return None
+    try:
+        tj = json.load(open(path))
+    except Exception:
+        return None
+    if tj.get("workload_key") != key or tj.get("kernel_source_hash") != _kernel_hash():
+        return None
+    return tj.get("hbm_bytes_per_launch")
 
 
 def _lat(ms):
@@ -260,12 +281,15 @@ def bench_diff3d(args, W, K, np, torch):
                                 f"exp(N(0,0.5^2)), r~U[-5,0], p=2, tau=1e-3, tol {pr.tol:g}, IOP q={args.q}"),
                    "precision": args.precision, "seed": pr.seed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _traffic(os.path.join(ROOT, "profiles", "traffic_diff3d.json"),
+                                         f"diff3d-{args.precision}-q{args.q}"),
                      "kernel": "kiops_solve_kernel<Stencil3D>", "algorithmic_bytes_per_launch": alg,
                      "avg_launch_ms": sum(ms) / len(ms)},
         "latency_ms": _lat(ms),
         "solve": {k: st[k] for k in ("matvecs", "substeps", "rejections", "m_last", "grid_blocks")},
     }
+    _calibrate_copy(args, torch, out)
     print(json.dumps(out), flush=True)
 
 

@@ -8,8 +8,11 @@
 // flat index x + nx (y + ny z).  Along an axis of length 1 both differences
 // vanish, which is what the wrapped neighbour (the cell itself) gives.
 //
-// Tiling (2.5-D): a workgroup owns a 64 x 4 column of the xy plane over a chunk
-// of z planes and marches through it in z.  LDS holds rolling windows
+// Tiling (2.5-D): a workgroup owns a 32 x 8 column of the xy plane over a chunk
+// of z planes and marches through it in z (32 x 8 rather than 64 x 4: the
+// halo-2 planes of R_{kp-1} and kappa are 36 x 12 = 1.69 tile areas instead of
+// 68 x 8 = 2.13, and the halo rows re-read by neighbouring tiles are most of
+// the traffic above the algorithmic bytes).  LDS holds rolling windows
 // of planes: R_{kp-1} (3 planes) and kappa (4 planes) over the tile plus an xy
 // halo of two, and R_kp (3 planes) over the tile plus an xy halo of one.  For
 // each plane z the workgroup loads plane z+1 of R_{kp-1} and kappa, forms R_kp
@@ -27,7 +30,8 @@ namespace kiops {
 
 template <typename T, int PB>
 struct Stencil3D {
-  static constexpr int TX = 64, TY = 4;
+  static constexpr int TX = 32, TY = 8;
+  static_assert(TX * TY == kThreads && (TX & (TX - 1)) == 0, "one tile position per thread");
   static constexpr int RX = TX + 4, RY = TY + 4, RP = RX * RY;   // halo-2 plane (R_{kp-1}, kappa)
   static constexpr int SX = TX + 2, SY = TY + 2, SP = SX * SY;   // halo-1 plane (R_kp)
   static constexpr int kRingPos = SP - TX * TY;                   // halo-1 positions outside the tile
@@ -102,7 +106,7 @@ struct Stencil3D {
     T* sX = lds + 7 * RP;        // 3 planes of SP
     const int t = threadIdx.x;
     const int tcx = t & (TX - 1);
-    const int tcy = t >> 6;
+    const int tcy = t / TX;
     const bool first = c.first != 0;
     const bool has_kappa = kappa != nullptr;
     const uint64_t nb = (uint64_t)N * sizeof(T);
