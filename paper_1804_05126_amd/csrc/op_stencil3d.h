@@ -11,8 +11,8 @@
 // Tiling (2.5-D): a workgroup owns a 32 x 8 column of the xy plane over a chunk
 // of z planes and marches through it in z (32 x 8 rather than 64 x 4: the
 // halo-2 planes of R_{kp-1} and kappa are 36 x 12 = 1.69 tile areas instead of
-// 68 x 8 = 2.13, and the halo rows re-read by neighbouring tiles are most of
-// the traffic above the algorithmic bytes).  LDS holds rolling windows
+// 68 x 8 = 2.13, and a plane takes two region loads per thread instead of
+// three).  LDS holds rolling windows
 // of planes: R_{kp-1} (3 planes) and kappa (4 planes) over the tile plus an xy
 // halo of two, and R_kp (3 planes) over the tile plus an xy halo of one.  For
 // each plane z the workgroup loads plane z+1 of R_{kp-1} and kappa, forms R_kp
