@@ -253,6 +253,18 @@ __device__ inline void reduce_partials(const KParams& P, double* out, double* ld
 #pragma unroll
       for (int d = 0; d < kDotSlots; ++d) acc[d] += v[u][d];
   }
+  if (w + kThreads < rows) {   // two rows per thread (512 workgroups): all loads in flight at once
+    double v[2][kDotSlots];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int d = 0; d < kDotSlots; ++d) v[u][d] = P.partials[(int64_t)(w + u * kThreads) * P.ndot_stride + d];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int d = 0; d < kDotSlots; ++d) acc[d] += v[u][d];
+    w += 2 * kThreads;
+  }
   for (; w < rows; w += kThreads)
 #pragma unroll
     for (int d = 0; d < kDotSlots; ++d) acc[d] += P.partials[(int64_t)w * P.ndot_stride + d];
