@@ -194,11 +194,13 @@ kiops_status kiops_phi_combination_times(kiops_operator* op, int n, const double
 
 /*
  * Batched form: many independent phi-combinations in one persistent launch.
- * The grid is split into groups of group_size workgroups; each group runs its
- * share of the problems one after another (each problem is a full Algorithm 1
- * solve on that group, with the group's own grid barrier), so problems of
- * different sizes proceed concurrently.  Problems are assigned to groups by
- * longest-estimated-work first.  All operators of a batch must have the same
+ * The grid is split into groups of workgroups; each group runs its share of
+ * the problems one after another (each problem is a full Algorithm 1 solve on
+ * that group, with the group's own grid barrier), so problems of different
+ * sizes proceed concurrently.  A problem with a large share of the estimated
+ * work (N (1 + tau ||A||_1)) gets a group of its own of group_size * 2^k
+ * workgroups (such groups take at most half of the launch); the others share
+ * groups of group_size, assigned by longest-estimated-work first.  All operators of a batch must have the same
  * kind and precision; p may differ (0..KIOPS_P_MAX), q in 0..4.
  */
 typedef struct {

@@ -560,11 +560,13 @@ __global__ void small_expm_kernel(const double* Hs, int n, double tau, double* F
 
 struct BatchPlan {
   int gs = 0, ng = 0, pb = 0, m_min = 0, m_max = 0, max_sub = 0;
+  int nwg = 0;                          // workgroups of the launch
   const void* fn = nullptr;
+  std::vector<int> gsize, wg0;          // per group: workgroups and the first of them
   std::vector<int> group_of;            // problem -> group
   std::vector<std::vector<int>> members;
   std::vector<size_t> group_off;        // group workspace offsets
-  size_t ctrl_off = 0, block_off = 0, queue_off = 0, total = 0;
+  size_t ctrl_off = 0, block_off = 0, queue_off = 0, map_off = 0, total = 0;
 };
 
 size_t ctrl_stride() { return align_up(sizeof(Ctrl)); }
@@ -620,19 +622,58 @@ kiops_status plan_batch(int count, const kiops_problem* probs, const kiops_optio
   }
   if (gs > total) return KIOPS_ERR_INVALID_ARG;
   B.gs = gs;
-  B.ng = std::min(total / gs, count);
-  // longest estimated work first, each to the least-loaded group
+  std::vector<double> est(count);
+  double tot = 0.0;
+  for (int i = 0; i < count; ++i) tot += (est[i] = work_estimate(probs[i]));
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
-  std::vector<double> est(count);
-  for (int i = 0; i < count; ++i) est[i] = work_estimate(probs[i]);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return est[a] > est[b]; });
+  // Groups: a problem whose share of the estimated work exceeds what one
+  // group of gs workgroups gives it gets a group of its own, sized to its
+  // share (gs times a power of two, within its work tiles); dedicated groups
+  // take at most half of the workgroups.  The rest is split into groups of
+  // gs that share the other problems.  (One group size for all would leave
+  // the largest problem, in the batched workload a fifth of the work, on gs
+  // workgroups and set the batch's time.)
+  auto pow2_floor = [](int64_t v) { int64_t r = 1; while (2 * r <= v) r *= 2; return (int)r; };
+  std::vector<int> dedicated;           // problem of each dedicated group
+  int used = 0;
+  const int budget = total / 2;
+  if (std::getenv("KIOPS_BATCH_UNIFORM") == nullptr) {   // experiment override: groups of gs only
+    for (int i : order) {
+      if ((int)dedicated.size() + 1 >= count) break;   // keep one problem for the shared groups
+      int want = gs;   // the power of two nearest (in ratio) to its share of the workgroups
+      while (want < budget && 1.5 * (double)want < (double)total * est[i] / tot) want *= 2;
+      want = std::min(want, std::max(gs, pow2_floor(std::max<int64_t>(1, work_tiles(probs[i].op)))));
+      while (want > gs && used + want > budget) want /= 2;
+      if (want <= gs) break;             // sorted: every later problem wants less
+      dedicated.push_back(i);
+      B.gsize.push_back(want);
+      used += want;
+    }
+  }
+  const int nshared = std::max(1, std::min((total - used) / gs, count - (int)dedicated.size()));
+  for (int k = 0; k < nshared; ++k) B.gsize.push_back(gs);
+  B.ng = (int)B.gsize.size();
+  B.wg0.assign(B.ng, 0);
+  for (int g = 1; g < B.ng; ++g) B.wg0[g] = B.wg0[g - 1] + B.gsize[g - 1];
+  B.nwg = B.wg0[B.ng - 1] + B.gsize[B.ng - 1];
+  if (B.nwg > total) return KIOPS_ERR_INVALID_ARG;
+  // dedicated problems first, then longest estimated work first, each to the
+  // shared group that would finish it first
   std::vector<double> load(B.ng, 0.0);
-  B.group_of.assign(count, 0);
+  B.group_of.assign(count, -1);
   B.members.assign(B.ng, {});
+  for (size_t k = 0; k < dedicated.size(); ++k) {
+    B.group_of[dedicated[k]] = (int)k;
+    B.members[k].push_back(dedicated[k]);
+    load[k] = est[dedicated[k]];
+  }
+  const int first_shared = (int)dedicated.size();
   for (int i : order) {
-    int g = 0;
-    for (int h = 1; h < B.ng; ++h)
+    if (B.group_of[i] >= 0) continue;
+    int g = first_shared;
+    for (int h = first_shared + 1; h < B.ng; ++h)
       if (load[h] < load[g] || (load[h] == load[g] && B.members[h].size() < B.members[g].size())) g = h;
     if ((int)B.members[g].size() >= kGroupQueueLen) return KIOPS_ERR_UNSUPPORTED;
     B.group_of[i] = g;
@@ -647,7 +688,7 @@ kiops_status plan_batch(int count, const kiops_problem* probs, const kiops_optio
   for (int g = 0; g < B.ng; ++g) {
     size_t need = 0;
     for (int i : B.members[g]) {
-      const Layout L = make_layout(probs[i].op, probs[i].p, probs[i].q, B.m_max, gs);
+      const Layout L = make_layout(probs[i].op, probs[i].p, probs[i].q, B.m_max, B.gsize[g]);
       need = std::max(need, L.total);
     }
     B.group_off[g] = off;
@@ -659,6 +700,8 @@ kiops_status plan_batch(int count, const kiops_problem* probs, const kiops_optio
   off = align_up(off + (size_t)4096 * count);
   B.queue_off = off;
   off = align_up(off + sizeof(GroupQueue) * B.ng);
+  B.map_off = off;
+  off = align_up(off + sizeof(int) * (size_t)B.nwg);
   B.total = off;
   return KIOPS_OK;
 }
@@ -678,6 +721,8 @@ kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B
   for (int g = 0; g < B.ng; ++g) {
     GroupQueue& Q = queues[g];
     std::memset(&Q, 0, sizeof(GroupQueue));
+    Q.wg0 = B.wg0[g];
+    Q.gsize = B.gsize[g];
     Q.tail = (unsigned)B.members[g].size();
     Q.closed = 1;
     Q.idle_limit = clock_hz * 60ull;
@@ -685,7 +730,7 @@ kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B
     for (size_t e = 0; e < B.members[g].size(); ++e) {
       const int i = B.members[g][e];
       const kiops_problem& pr = probs[i];
-      const Layout L = make_layout(pr.op, pr.p, pr.q, B.m_max, B.gs);
+      const Layout L = make_layout(pr.op, pr.p, pr.q, B.m_max, B.gsize[g]);
       KParams P = make_params(pr.op, L, base, pr.tau, pr.p, pr.V, pr.tol, pr.m_init, pr.q, B.m_min, B.m_max,
                               B.max_sub, kModeSolve, pr.w);
       P.ctrl = reinterpret_cast<Ctrl*>(ws + B.ctrl_off + ctrl_stride() * i);
@@ -697,13 +742,18 @@ kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B
     }
     // the group's barrier words: zero (same offsets for every layout of the group)
     const Layout L0 = make_layout(probs[B.members[g][0]].op, probs[B.members[g][0]].p,
-                                  probs[B.members[g][0]].q, B.m_max, B.gs);
+                                  probs[B.members[g][0]].q, B.m_max, B.gsize[g]);
     if (!hip_ok(hipMemsetAsync(base + L0.bar, 0, L0.H - L0.bar, stream))) return KIOPS_ERR_DEVICE;
   }
+  std::vector<int> wg_group(B.nwg);
+  for (int g = 0; g < B.ng; ++g)
+    for (int k = 0; k < B.gsize[g]; ++k) wg_group[B.wg0[g] + k] = g;
   if (!hip_ok(hipMemcpyAsync(ws + B.ctrl_off, ctrls.data(), ctrls.size(), hipMemcpyHostToDevice, stream)) ||
       !hip_ok(hipMemcpyAsync(ws + B.block_off, blocks.data(), blocks.size(), hipMemcpyHostToDevice, stream)) ||
       !hip_ok(hipMemcpyAsync(ws + B.queue_off, queues.data(), sizeof(GroupQueue) * B.ng, hipMemcpyHostToDevice,
-                             stream)))
+                             stream)) ||
+      !hip_ok(hipMemcpyAsync(ws + B.map_off, wg_group.data(), sizeof(int) * wg_group.size(),
+                             hipMemcpyHostToDevice, stream)))
     return KIOPS_ERR_DEVICE;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ms_out) {
@@ -711,9 +761,9 @@ kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B
     hipEventRecord(e0, stream);
   }
   GroupQueue* dq = reinterpret_cast<GroupQueue*>(ws + B.queue_off);
-  int gs = B.gs;
-  void* args[] = {&dq, &gs};
-  if (!hip_ok(hipLaunchCooperativeKernel(B.fn, dim3(B.ng * B.gs), dim3(kThreads), args, 0, stream)))
+  const int* dmap = reinterpret_cast<const int*>(ws + B.map_off);
+  void* args[] = {&dq, &dmap};
+  if (!hip_ok(hipLaunchCooperativeKernel(B.fn, dim3(B.nwg), dim3(kThreads), args, 0, stream)))
     return KIOPS_ERR_DEVICE;
   if (ms_out) hipEventRecord(e1, stream);
   if (!hip_ok(hipMemcpyAsync(ctrls.data(), ws + B.ctrl_off, ctrls.size(), hipMemcpyDeviceToHost, stream)))
@@ -721,7 +771,7 @@ kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B
   std::vector<unsigned> aborts(B.ng, 0);
   for (int g = 0; g < B.ng; ++g) {
     const Layout L0 = make_layout(probs[B.members[g][0]].op, probs[B.members[g][0]].p,
-                                  probs[B.members[g][0]].q, B.m_max, B.gs);
+                                  probs[B.members[g][0]].q, B.m_max, B.gsize[g]);
     const Barrier* bar = reinterpret_cast<const Barrier*>(ws + B.group_off[g] + L0.bar);
     if (!hip_ok(hipMemcpyAsync(&aborts[g], &bar->abort, sizeof(unsigned), hipMemcpyDeviceToHost, stream)))
       return KIOPS_ERR_DEVICE;
@@ -739,7 +789,7 @@ kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B
     Ctrl c;
     std::memcpy(&c, ctrls.data() + ctrl_stride() * i, sizeof(Ctrl));
     if (aborts[B.group_of[i]] && c.status == KIOPS_OK) c.status = KIOPS_ERR_DEVICE;
-    if (stats) fill_stats(c, B.gs, (double)clock_hz, &stats[i]);
+    if (stats) fill_stats(c, B.gsize[B.group_of[i]], (double)clock_hz, &stats[i]);
     if (first == KIOPS_OK && c.status != KIOPS_OK) first = (kiops_status)c.status;
   }
   return first;

@@ -161,8 +161,10 @@ struct GroupQueue {
   unsigned exit_reason;     // why the group left: 1 closed, 2 idle (device)
   unsigned exit_entry;      // the entry it was waiting for then (device)
   unsigned idle_sleep;      // s_sleep(127) repeats between two polls of an idle group
+  int wg0;                  // batched form: first workgroup of the group
+  int gsize;                // batched form: workgroups of the group
   unsigned pad0;
-  uint64_t pad1[11];        // one 128-byte line for the words above
+  uint64_t pad1[10];        // one 128-byte line for the words above
   const unsigned char* blocks[kGroupQueueLen];
 };
 

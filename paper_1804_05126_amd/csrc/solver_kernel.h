@@ -1150,24 +1150,26 @@ __device__ __forceinline__ void solve_block(const KParams* __restrict__ Pp, cons
 }
 
 // Groups of workgroups, each running the solves queued for it one after
-// another (batched and served forms).  Group g is workgroups
-// [g * group_size, (g+1) * group_size); its queue lists parameter blocks
+// another (batched form).  Group g is workgroups [wg0, wg0 + gsize) of its
+// queue (wg_group[b] names the group of workgroup b); its queue lists parameter blocks
 // (KParams, operator struct at +2048) that the host prepared for that group's
 // workspace.  A group waits for entry e until the host has published it
 // (queue tail > e) or has closed the queue; it reports entry e done by
 // storing e + 1 into `done`.  Waiting is bounded by the queue's idle limit.
 template <class Op, typename T>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(Op::kWavesPerEU, 8)))
-kiops_group_kernel(GroupQueue* __restrict__ queues, int group_size) {
+kiops_group_kernel(GroupQueue* __restrict__ queues, const int* __restrict__ wg_group) {
   constexpr int kLds = Op::kLdsDoubles > kLdsDoubles ? Op::kLdsDoubles : kLdsDoubles;
   __shared__ double lds[kLds];
   __shared__ PassCtx<T> pctx;
   __shared__ SmallState S;
   __shared__ int s_phase;
   __shared__ long long s_entry;
-  const int g = (int)blockIdx.x / group_size;
-  set_vgrid((int)blockIdx.x % group_size, group_size);
+  // groups are contiguous runs of workgroups of different sizes (a large
+  // problem gets a larger group); wg_group maps a workgroup to its group
+  const int g = uniform(wg_group[blockIdx.x]);
   GroupQueue& Q = queues[g];
+  set_vgrid((int)blockIdx.x - uniform(Q.wg0), uniform(Q.gsize));
   unsigned epoch = 0;
   for (unsigned e = 0;; ++e) {
     if (threadIdx.x < 64) {
