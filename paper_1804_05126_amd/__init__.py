@@ -240,7 +240,10 @@ def phi_batch(problems: Sequence[dict], group_size: int = 0, m_min: int = 0, m_m
               max_substeps: int = 0, stream=None):
     """Batched form: every problem (a dict with op, tau, vectors and optionally
     tol, m_init, q, out) solved in one persistent launch.  Returns
-    (list of w, list of stats dicts, status, plan) with plan = (groups, group_size)."""
+    (list of w, list of stats dicts, status, plan) with plan = (groups,
+    group_size): the number of groups and the size of the shared groups (a
+    problem with a large share of the work runs on a larger group of its own;
+    stats[i]["grid_blocks"] is the size of the group that solved problem i)."""
     torch = _torch()
     lib = _lib.load()
     arr, keep, outs = _batch_problems(problems)
