@@ -6,7 +6,7 @@
 
 namespace kiops {
 
-const void* kernels_stencil2d(bool mixed, int pb, bool group);
+const void* kernels_stencil2d(bool mixed, int pb, bool group, bool wide);   // wide: IOP windows of 3, 4 (one-solve kernel)
 const void* kernels_stencil3d(bool mixed, int pb, bool group);
 const void* kernels_csr(bool mixed, int pb, bool group);
 const void* kernels_serve();   // served form: 2-D and 3-D stencils, FP64 and mixed, p <= 4
@@ -23,6 +23,16 @@ const void* pick_kernel(bool mixed, int pb, bool group) {
     default: return mixed ? KIOPS_K(float, 8) : KIOPS_K(double, 8);
   }
 #undef KIOPS_K
+}
+// the one-solve kernel only
+template <template <typename, int> class OP>
+const void* pick_solve_kernel(bool mixed, int pb) {
+  switch (pb) {
+    case 0: return mixed ? (const void*)kiops_solve_kernel<OP<float, 0>, float> : (const void*)kiops_solve_kernel<OP<double, 0>, double>;
+    case 2: return mixed ? (const void*)kiops_solve_kernel<OP<float, 2>, float> : (const void*)kiops_solve_kernel<OP<double, 2>, double>;
+    case 4: return mixed ? (const void*)kiops_solve_kernel<OP<float, 4>, float> : (const void*)kiops_solve_kernel<OP<double, 4>, double>;
+    default: return mixed ? (const void*)kiops_solve_kernel<OP<float, 8>, float> : (const void*)kiops_solve_kernel<OP<double, 8>, double>;
+  }
 }
 #endif
 

@@ -117,17 +117,20 @@ int zchunks(const kiops_operator* op, int nwg) {
   return (int)base;
 }
 
-// Kernel of an operator for p-bucket pb: the one-solve kernel or the group kernel.
-const void* kernel_for_bucket(const kiops_operator* op, int pb, bool group) {
+// Kernel of an operator for p-bucket pb: the one-solve kernel or the group
+// kernel; wide: the 5-point one-solve kernel for IOP windows of 3 and 4.
+const void* kernel_for_bucket(const kiops_operator* op, int pb, bool group, bool wide = false) {
   const bool mixed = op->d.precision == KIOPS_MIXED;
   if (uses_3d(op)) return kernels_stencil3d(mixed, pb, group);
-  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) return kernels_stencil2d(mixed, pb, group);
+  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) return kernels_stencil2d(mixed, pb, group, wide);
   if (op->d.kind == KIOPS_OP_CSR) return kernels_csr(mixed, pb, group);
   return nullptr;
 }
 
-// The kernel instantiation that serves an operator and p.
-const void* kernel_for(const kiops_operator* op, int p) { return kernel_for_bucket(op, p_bucket(p), false); }
+// The kernel instantiation that serves an operator, p and the IOP window q.
+const void* kernel_for(const kiops_operator* op, int p, int q = 2) {
+  return kernel_for_bucket(op, p_bucket(p), false, q == 3 || q == 4);
+}
 
 int64_t work_tiles(const kiops_operator* op) {
   if (uses_3d(op)) {
@@ -445,7 +448,7 @@ kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, c
   std::memcpy(host_block, &P, sizeof(KParams));
   KParams* dP = reinterpret_cast<KParams*>(ws + L.params);
   void* dOp = ws + L.params + 2048;
-  const void* fn = kernel_for(op, p);
+  const void* fn = kernel_for(op, p, P.q);
   if (!fn) return KIOPS_ERR_UNSUPPORTED;
   kiops_status st = stage_op_block(op, p, p_bucket(p), V, ws, L, host_block);
   if (st != KIOPS_OK) return st;

@@ -25,8 +25,13 @@
 
 namespace kiops {
 
-template <typename T, int PB>
-struct Stencil2D {
+// kWide: the instantiation for windows of 3 or 4 vectors (IOP q = 3, 4), which
+// loads the one or two vectors older than R_{kp-2} with the tile, like the
+// other arrays, and reuses them and R_{kp-2} for the window's inner products;
+// a separate kernel, so that the common window of 2 keeps its own register
+// allocation (the same code in one kernel cost q = 2 2%, measured).
+template <typename T, int PB, bool kWide>
+struct Stencil2DT {
   static constexpr int TX = 64, TY = 16;
   static constexpr int RX = TX + 4, RY = TY + 4;   // halo-2 region (R_{kp-1})
   static constexpr int SX = TX + 2, SY = TY + 2;   // halo-1 region (R_kp)
@@ -80,6 +85,10 @@ struct Stencil2D {
     const uint64_t nb = (uint64_t)N * sizeof(T);
     const bool has_old = !first && c.flo < c.src;          // R_{kp-2} in the window
     const bool more_old = !first && c.flo < c.src - 1;     // windows wider than 2
+    const int n_extra = more_old ? c.src - 1 - c.flo : 0;   // vectors older than R_{kp-2}
+    const bool near_old = kWide && n_extra > 0 && n_extra <= 2;
+    const __amdgpu_buffer_rsrc_t rsE1 = make_rsrc(near_old ? bp.get(c.flo) : nullptr, nb);
+    const __amdgpu_buffer_rsrc_t rsE2 = make_rsrc(near_old && n_extra == 2 ? bp.get(c.flo + 1) : nullptr, nb);
     const __amdgpu_buffer_rsrc_t rsR = make_rsrc(first ? nullptr : bp.get(c.src), nb);
     const __amdgpu_buffer_rsrc_t rsO = make_rsrc(has_old ? bp.get(c.src - 1) : nullptr, nb);
     const __amdgpu_buffer_rsrc_t rsW = make_rsrc(first ? w : nullptr, (uint64_t)N * 8);
@@ -123,6 +132,7 @@ struct Stencil2D {
       }
       uint32_t goff[kPos];
       T rv[kPos], ov[kPos], bv[kPos][PB > 0 ? PB : 1];
+      T e1[kWide ? kPos : 1], e2[kWide ? kPos : 1];
 #pragma unroll
       for (int q = 0; q < kPos; ++q) {
         const int gx = wrap_index(x0 + prx[q], nx);
@@ -134,6 +144,14 @@ struct Stencil2D {
         else ov[q] = buf_ld(rsO, goff[q], T(0));
 #pragma unroll
         for (int k = 0; k < PB; ++k) bv[q][k] = buf_ld(rsB[k], goff[q], T(0));
+        if constexpr (kWide) {
+          e1[q] = T(0);
+          e2[q] = T(0);
+          if (near_old) {
+            e1[q] = buf_ld(rsE1, goff[q], T(0));
+            if (n_extra == 2) e2[q] = buf_ld(rsE2, goff[q], T(0));
+          }
+        }
       }
       // ---- R_{kp-1} region into LDS
       if (!first) {
@@ -171,7 +189,12 @@ struct Stencil2D {
             X = c.a * U;
             X = fma(c.bw[c.src], ctr, X);
             if (has_old) X = fma(c.bw[c.src - 1], ov[q], X);
-            if (more_old) {
+            if (near_old) {
+              if constexpr (kWide) {
+                X = fma(c.bw[c.flo], e1[q], X);
+                if (n_extra == 2) X = fma(c.bw[c.flo + 1], e2[q], X);
+              }
+            } else if (more_old) {
               // older window vectors (a full window streams every earlier
               // vector: eight loads in flight at a time)
               int i = c.flo;
@@ -212,8 +235,17 @@ struct Stencil2D {
         for (int d = 0; d < kWinMax - 1; ++d) {
           if (d < c.ngd) {
             const int idx = c.dlo + d;
-            const double Rv = (idx == c.src) ? (double)sR[(ry + 2) * RX + (cx + 2)]
-                                             : (double)buf_ld(make_rsrc(bp.get(idx), nb), goff[i], T(0));
+            double Rv;
+            if constexpr (kWide) {
+              if (idx == c.src) Rv = (double)sR[(ry + 2) * RX + (cx + 2)];
+              else if (idx == c.src - 1 && has_old) Rv = (double)ov[i];
+              else if (near_old && idx == c.flo) Rv = (double)e1[i];
+              else if (near_old && n_extra == 2 && idx == c.flo + 1) Rv = (double)e2[i];
+              else Rv = (double)buf_ld(make_rsrc(bp.get(idx), nb), goff[i], T(0));
+            } else {
+              Rv = (idx == c.src) ? (double)sR[(ry + 2) * RX + (cx + 2)]
+                                  : (double)buf_ld(make_rsrc(bp.get(idx), nb), goff[i], T(0));
+            }
             acc.G[d] = fma(Rv, Xd, acc.G[d]);
             acc.C[d] = fma(Rv, Ud, acc.C[d]);
           }
@@ -223,5 +255,10 @@ struct Stencil2D {
     }
   }
 };
+
+template <typename T, int PB>
+using Stencil2D = Stencil2DT<T, PB, false>;
+template <typename T, int PB>
+using Stencil2DWide = Stencil2DT<T, PB, true>;
 
 }  // namespace kiops
