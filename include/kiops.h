@@ -112,7 +112,7 @@ typedef struct {
   int32_t rejections;     /* rejected attempts */
   int32_t expms;          /* small exponentials computed */
   int32_t breakdowns;     /* happy breakdowns (Algorithm 2) */
-  int32_t grid_blocks;    /* workgroups of the persistent launch */
+  int32_t grid_blocks;    /* workgroups that ran the solve (the launch, or the batched group) */
   int64_t matvecs;        /* products with A~ */
   double last_omega;      /* scaled error of the last attempt, Eq. (39) */
   double t_reached;       /* T_now at exit (== tau on success) */
