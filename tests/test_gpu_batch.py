@@ -118,3 +118,23 @@ def test_full_batch_workload_matches_single_solves_and_oracle():
         pr = prs[i]
         ref = phi_combination_arnoldi(operators.make_apply(pr.op), pr.tau, pr.vectors, tol_o=1e-12)
         assert rel(ws[i].cpu().numpy(), ref) <= 1e-8, (pr.name, rel(ws[i].cpu().numpy(), ref))
+
+
+def test_batch_dominant_problem_gets_own_group():
+    """Two problems, one with nearly all of the work: the plan gives it a
+    group of its own (larger than the shared groups) and both results still
+    match the same problems solved alone (the small one also the dense route)."""
+    import paper_1804_05126_amd as K
+    big = W.adr2d_problem(256, 3, 2e-2, seed=4201)
+    small = W.adr2d_problem(16, 2, 1e-2, seed=4202)
+    probs = _problems([big, small])
+    announce("batch of a dominant and a small problem")
+    ws, stats, status, plan = K.phi_batch(probs, group_size=8)
+    assert status == 0
+    assert stats[0]["grid_blocks"] > 8 and stats[1]["grid_blocks"] == 8, (stats[0]["grid_blocks"], stats[1]["grid_blocks"])
+    for pr, pb, w in zip((big, small), probs, ws):
+        single, st, s1 = K.phi_combination(pb["op"], pr.tau, pb["vectors"], tol=pr.tol)
+        assert s1 == 0
+        assert rel(w.cpu().numpy(), single.cpu().numpy()) <= 2e-8
+    ref = augmented.phi_combination_dense(operators.dense(small.op), small.tau, small.vectors)
+    assert rel(ws[1].cpu().numpy(), ref) <= 1e-8
