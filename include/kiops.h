@@ -320,6 +320,21 @@ kiops_status kiops_iop_basis(kiops_operator* op, int p, const double* const* V, 
 kiops_status kiops_small_expm(int n, const double* Hs, double tau, double* F, double* scratch,
                               void* hip_stream);
 
+/*
+ * kiops_stream_probe: dst[i] = src[0][i] + ... + src[nsrc-1][i], i < n, one
+ *   plain unit-stride streaming kernel (16-byte loads, several in flight per
+ *   thread) on `blocks` workgroups of 256 threads, enqueued on hip_stream and
+ *   not waited for.  Diagnostics: it measures the HBM bandwidth a streaming
+ *   kernel reaches on this device (nsrc reads + 1 write per element), the
+ *   ceiling the solver's passes are compared with, and is a kernel of known
+ *   traffic for scaling hardware byte counters.  src[s] and dst are device
+ *   arrays of n doubles, 16-byte aligned, caller-owned, dst not overlapping
+ *   any src; 1 <= nsrc <= 8; n even.  Errors: INVALID_ARG (nothing launched),
+ *   DEVICE (the launch failed).
+ */
+kiops_status kiops_stream_probe(const double* const* src, int nsrc, double* dst, int64_t n, int blocks,
+                                void* hip_stream);
+
 /* Host-side copy of the device step controller (Algorithm 4), for tests. */
 typedef struct {
   double T_end, tol, T_now, tau;

@@ -17,6 +17,7 @@ Modules:
   augmented  Theorem 1: the augmented matrix (13) and the dense exact result (14)
   spectral   exact result for constant-coefficient periodic stencils via the DFT
   arnoldi    exact-to-tolerance result for large N via full-Arnoldi Krylov
+  lanczos    exact-to-tolerance result for symmetric A, one Lanczos process per term
   iop        Algorithm 2 (incomplete orthogonalization, window q)
   controller Algorithm 4 with Sections 3.5-3.6 (acceptance, step size, dimension)
   kiops      Algorithm 1 (Task II) assembled from the pieces above

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import KiopsError  # noqa: F401
 
 __all__ = ["Operator", "phi_combination", "phi_batch", "batch_tune", "Server", "iop_basis", "small_expm",
-           "controller_decide", "KiopsError"]
+           "stream_probe", "controller_decide", "KiopsError"]
 
 
 def _torch():
@@ -383,6 +383,22 @@ def small_expm(Hs, tau: float, stream=None):
                                     C.c_void_p(_ptr(scratch)), C.c_void_p(s.cuda_stream)),
                "kiops_small_expm")
     return F
+
+
+def stream_probe(srcs: Sequence, dst, blocks: int, stream=None) -> None:
+    """dst = sum(srcs) by the library's plain streaming kernel on `blocks`
+    workgroups (enqueued on the stream, not waited for); a bandwidth probe."""
+    torch = _torch()
+    lib = _lib.load()
+    n = int(dst.numel())
+    _require_cuda_f64(dst, n, "dst")
+    arr = (C.c_void_p * len(srcs))()
+    for k, t in enumerate(srcs):
+        _require_cuda_f64(t, n, f"src[{k}]")
+        arr[k] = _ptr(t)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _lib.check(lib.kiops_stream_probe(arr, len(srcs), C.c_void_p(_ptr(dst)), n, int(blocks),
+                                      C.c_void_p(s.cuda_stream)), "kiops_stream_probe")
 
 
 def controller_decide(state: dict, j: int, eps: float, breakdown: bool) -> dict:

@@ -116,6 +116,8 @@ SIGNATURES = [
                                   C.POINTER(C.c_double)]),
     ("kiops_small_expm", C.c_int, [C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
                                    C.c_void_p]),
+    ("kiops_stream_probe", C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p, C.c_int64, C.c_int,
+                                     C.c_void_p]),
     ("kiops_controller_decide", C.c_int, [C.POINTER(CtrlIn), C.c_int, C.c_double, C.c_int,
                                           C.POINTER(CtrlOut)]),
     ("kiops_batch_plan", C.c_int, [C.c_int, C.POINTER(Problem), C.POINTER(Options), C.c_int,

@@ -1041,7 +1041,9 @@ kiops_status kiops_create_operator(const kiops_operator_desc* desc, void* hip_st
     if (d.nx < 1 || d.ny < 1 || d.nz < 1 || !(d.h > 0.0) || !std::isfinite(d.h)) return KIOPS_ERR_INVALID_ARG;
     if (d.kind == KIOPS_OP_STENCIL2D_5PT && d.nz != 1) return KIOPS_ERR_INVALID_ARG;
     if (d.nx > (1 << 30) || d.ny > (1 << 30) || d.nz > (1 << 30)) return KIOPS_ERR_INVALID_ARG;
-    N = d.nx * d.ny * d.nz;
+    int64_t nxy = 0;
+    if (__builtin_mul_overflow(d.nx, d.ny, &nxy) || __builtin_mul_overflow(nxy, d.nz, &N))
+      return KIOPS_ERR_INVALID_ARG;
     // the passes address every array with 32-bit byte offsets
     if (N * (int64_t)sizeof(double) >= ((int64_t)1 << 32)) return KIOPS_ERR_INVALID_ARG;
     if (!std::isfinite(d.diff) || !std::isfinite(d.adv[0]) || !std::isfinite(d.adv[1]) ||

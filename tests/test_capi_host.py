@@ -61,6 +61,30 @@ def test_null_arguments_rejected_without_device():
     assert lib.kiops_destroy_operator(None) == 1
 
 
+def test_grid_size_product_overflow_rejected():
+    # each side within 2^30, but nx*ny*nz = 2^66 wraps a 64-bit product
+    L, lib = _lib()
+    out = ctypes.c_void_p()
+    d = L.OperatorDesc()
+    d.kind = L.OP_STENCIL3D_7PT
+    d.nx = d.ny = d.nz = 1 << 22
+    d.h = 1.0
+    assert lib.kiops_create_operator(ctypes.byref(d), None, ctypes.byref(out)) == 1
+    d.nx = d.ny = d.nz = 1 << 11                  # 2^33 points: 8 N reaches 4 GiB
+    assert lib.kiops_create_operator(ctypes.byref(d), None, ctypes.byref(out)) == 1
+    assert not out.value
+
+
+def test_stream_probe_rejects_bad_arguments_without_device():
+    _, lib = _lib()
+    arr = (ctypes.c_void_p * 1)(16)
+    assert lib.kiops_stream_probe(None, 1, ctypes.c_void_p(16), 64, 8, None) == 1
+    assert lib.kiops_stream_probe(arr, 0, ctypes.c_void_p(16), 64, 8, None) == 1
+    assert lib.kiops_stream_probe(arr, 1, None, 64, 8, None) == 1
+    assert lib.kiops_stream_probe(arr, 1, ctypes.c_void_p(16), 63, 8, None) == 1      # odd n
+    assert lib.kiops_stream_probe(arr, 1, ctypes.c_void_p(24), 64, 8, None) == 1      # misaligned dst
+
+
 GOLDEN = os.path.join(ROOT, "tests", "golden", "controller_cases.json")
 
 
