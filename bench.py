@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--q", type=int, default=2)
     ap.add_argument("--precision", type=str, default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-substeps", type=int, default=2)
+    ap.add_argument("--cpu-sample-substeps", type=int, default=1,
+                    help="substeps of the one-thread CPU oracle sample")
     ap.add_argument("--traffic-json", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--workload", choices=("adr2d", "diff3d", "batch", "serve", "small"), default="adr2d",
                     help="adr2d: the 2048^2 tau sweep (default); diff3d: the 256^3 variable-"
@@ -56,34 +57,69 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(pr_sample, sweep_taus, substeps):
-    """Time the oracle's exact-result route (full-Arnoldi Krylov, oracle/arnoldi.py)
-    on the first `substeps` substeps of the smallest-tau solve of the same
-    2048^2 problem, and extrapolate to the sweep: the substepped Krylov cost
-    grows about linearly with tau, so a sweep costs sum(tau)/tau_sample times
-    one solve, and one solve costs elapsed * tau_sample / t_reached."""
+def _host_info():
+    """nproc and the CPU model of the host (lscpu), for the baseline record."""
+    import subprocess
+    info = {"nproc": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(pr_sample, sweep_taus, one_thread_substeps):
+    """Time the oracle's exact-result route (full-Arnoldi Krylov, oracle/arnoldi.py,
+    as it stands) on one whole solve of the smallest-tau point of the sweep, on
+    the host's cores, and once more on one thread over its first substeps.
+
+    The oracle's stencil products are single-threaded NumPy; its orthogonal-
+    isation (tall-skinny products) runs on the BLAS thread pool.  The sweep rate
+    is the whole solve's time scaled by sum(tau) / tau_sample (the oracle's
+    substep count grows linearly in tau: each substep covers a bounded tau||A||);
+    the factor is stated in the record."""
     import numpy as np  # noqa: F401
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import operators
     from oracle.arnoldi import phi_combination_arnoldi
-    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
     ap = operators.make_apply(pr_sample.op)
+    blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     st = {}
     t0 = time.perf_counter()
-    phi_combination_arnoldi(ap, pr_sample.tau, pr_sample.vectors, tol_o=1e-3 * pr_sample.tol, m=48,
-                            stats=st, stop_after=substeps)
-    el = time.perf_counter() - t0
-    frac = st["t"] / pr_sample.tau
-    t_solve = el / max(frac, 1e-300)
-    t_sweep = t_solve * sum(sweep_taus) / pr_sample.tau
+    phi_combination_arnoldi(ap, pr_sample.tau, pr_sample.vectors, tol_o=1e-3 * pr_sample.tol, m=48, stats=st)
+    t_solve = time.perf_counter() - t0
+    st1 = {}
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        phi_combination_arnoldi(ap, pr_sample.tau, pr_sample.vectors, tol_o=1e-3 * pr_sample.tol, m=48,
+                                stats=st1, stop_after=one_thread_substeps)
+        t_one = time.perf_counter() - t1
+    factor = sum(sweep_taus) / pr_sample.tau
+    t_sweep = t_solve * factor
+    one_solve_est = t_one * pr_sample.tau / max(st1["t"], 1e-300)
     return {
         "value": len(sweep_taus) / t_sweep,
         "unit": "solves/s",
-        "cores": int(threads),
+        "cores": int(blas_threads),
         "kind": "oracle",
-        "sample": (f"oracle full-Arnoldi route (m=48, CGS2, tol_o=1e-11) on the 2048^2 problem at "
-                   f"tau={pr_sample.tau:g}: {st['substeps']} substeps, {st['matvecs']} products, "
-                   f"{el:.1f} s covering t={st['t']:.3g} of {pr_sample.tau:g}; extrapolated "
-                   f"linearly in tau to the 5-value sweep"),
+        "sample": (f"one whole solve of the same problem (N={pr_sample.n}) at tau={pr_sample.tau:g} by the oracle's full-Arnoldi "
+                   f"route (m=48, CGS2, tol_o=1e-11): {st['substeps']} substeps, {st['matvecs']} products, "
+                   f"{t_solve:.1f} s measured on {blas_threads} BLAS threads (stencil products single-threaded); "
+                   f"sweep rate = 5 / (that time x sum(tau)/tau = {factor:.1f})"),
+        "measured_solve_s": t_solve,
+        "measured_solves_per_s_at_tau": 1.0 / t_solve,
+        "sweep_extrapolation_factor": factor,
+        "one_thread": {"substeps": st1["substeps"], "products": st1["matvecs"], "seconds": t_one,
+                       "t_covered": st1["t"], "solve_s_estimate": one_solve_est},
+        "host": _host_info(),
     }
 
 
@@ -120,6 +156,8 @@ def main():
     w = torch.empty(pr.n, dtype=torch.float64, device=dev)
     tol = 1e-8 if args.precision == "fp64" else 1e-6
     stream = torch.cuda.current_stream()
+    elem = "double" if args.precision == "fp64" else "float"
+    kname = "Stencil2D" if args.q in (1, 2) else ("Stencil2DWide" if args.q in (3, 4) else "Stencil2D (full window)")
 
     def one_solve(tau):
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -157,14 +195,7 @@ def main():
         d["ms"].append(ms)
     for d in per_tau.values():
         d["ms"] = float(np.median(d["ms"]))
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            if tj.get("workload_side") == side and tj.get("kernel_source_hash") == _kernel_hash():
-                traffic = tj.get("hbm_bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = _traffic(args.traffic_json, f"adr2d-{side}-{args.precision}-q{args.q}")
     lat = sorted(times_ms)
     out = {
         "metric": METRIC,
@@ -182,7 +213,7 @@ def main():
         "config": {
             "workload": (f"2D ADR {side}^2 periodic (N={pr.n}), A=1e-2 L5 - 10(Dx+Dy) + diag(r), "
                          f"r~U[-1,0], p=3, b_k~N(0,1), tau sweep {taus}, tol {tol:g}, IOP q={args.q}, "
-                         f"m_init=10, m_max=128"),
+                         f"m_init=10, m_max={records[0][3]['m_max']}"),
             "solves_per_step": len(taus),
             "precision": args.precision,
             "seed": pr.seed,
@@ -194,7 +225,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "kiops_solve_kernel<Stencil2D<double>, double> (one persistent launch per solve)",
+            "kernel": f"kiops_solve_kernel<{kname}<{elem}>, {elem}> (one persistent launch per solve)",
             "algorithmic_bytes_per_launch": total_bytes / n_solves,
             "avg_launch_ms": total_ms / n_solves,
         },
@@ -205,20 +236,23 @@ def main():
     _calibrate_copy(args, torch, out)
     if not args.no_cpu_baseline:
         sample = W.cfg2(side, taus[0], q=args.q)
+        print("[bench] timing the CPU oracle (one whole solve)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sample, taus, args.cpu_sample_substeps)
     print(json.dumps(out), flush=True)
 
 
 def _calibrate_copy(args, torch, out):
-    """One plain elementwise copy of a known size after the timed region, so
-    that hardware byte counters can be scaled by what they read for it."""
+    """One plain streaming copy of a known size after the timed region, by the
+    library's own probe kernel (dst = src, 16-byte loads), so that hardware byte
+    counters can be scaled by what they read for it."""
     if args.calibrate_copy <= 0:
         return
+    import paper_1804_05126_amd as K
     nbytes = args.calibrate_copy << 20
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    torch.mul(src, 1.0, out=dst)      # elementwise kernel: reads and writes nbytes
+    K.stream_probe([src], dst, blocks=1024)      # reads and writes nbytes
     torch.cuda.synchronize()
     out["copy_calibration_bytes"] = nbytes
     del src, dst

@@ -130,7 +130,7 @@ typedef struct {
   int64_t barriers;
   double release_max_s, release_mean_s;
   int32_t status;          /* the solve's own status (useful for batched problems) */
-  int32_t reserved2;
+  int32_t m_max;           /* the largest basis size the solve allowed (the option, or the default) */
   /* With KIOPS_PROFILE=1 only (else 0): parts of time_epilogue_s after passes */
   double time_reduce_s;    /* reductions of the per-workgroup partial sums */
   double time_publish_s;   /* copies of the control block */

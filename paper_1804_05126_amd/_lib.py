@@ -65,7 +65,7 @@ class Stats(C.Structure):
         ("time_expm_s", C.c_double), ("arrive_max_s", C.c_double), ("arrive_mean_s", C.c_double),
         ("barriers", C.c_int64),
         ("release_max_s", C.c_double), ("release_mean_s", C.c_double),
-        ("status", C.c_int32), ("reserved2", C.c_int32),
+        ("status", C.c_int32), ("m_max", C.c_int32),
         ("time_reduce_s", C.c_double), ("time_publish_s", C.c_double), ("time_serial_s", C.c_double),
     ]
 

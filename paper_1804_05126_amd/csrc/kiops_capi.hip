@@ -17,6 +17,7 @@
 #include "../../include/kiops.h"
 #include "controller.h"
 #include "op_stencil2d.h"
+#include "op_stencil2d_march.h"
 #include "op_stencil3d.h"
 #include "op_csr.h"
 #include "kernel_table.h"
@@ -117,22 +118,51 @@ int zchunks(const kiops_operator* op, int nwg) {
   return (int)base;
 }
 
+// The row-marching 5-point pass (op_stencil2d_march.h) serves the one-solve
+// kernel of large constant-diffusivity 2-D grids with windows of one or two
+// vectors: strips of 256 columns, chunks of about 32 rows, enough items to
+// give every CU work.  KIOPS_MARCH=0 selects the tile pass instead, and
+// KIOPS_MARCH=2 the marching pass whenever the window allows it (tests).
+int march_chunks(const kiops_operator* op) {   // chunks of at most kChunkRows rows (the march unrolls them)
+  const int64_t c = Stencil2DMarch<double, 2>::kChunkRows;
+  return (int)std::max<int64_t>(1, (op->d.ny + c - 1) / c);
+}
+int64_t march_items(const kiops_operator* op) {
+  const int64_t W = Stencil2DMarch<double, 2>::W;
+  return (op->d.nx + W - 1) / W * march_chunks(op);
+}
+bool use_march(const kiops_operator* op, int q) {
+  if (op->d.kind != KIOPS_OP_STENCIL2D_5PT || op->d.kappa || (q != 1 && q != 2)) return false;
+  const char* e = std::getenv("KIOPS_MARCH");   // experiment / test override
+  const int mode = e ? std::atoi(e) : 1;
+  if (mode == 0) return false;
+  if (mode >= 2) return true;
+  return op->d.nx >= Stencil2DMarch<double, 2>::W && march_items(op) >= op->cus;
+}
+
 // Kernel of an operator for p-bucket pb: the one-solve kernel or the group
-// kernel; wide: the 5-point one-solve kernel for IOP windows of 3 and 4.
-const void* kernel_for_bucket(const kiops_operator* op, int pb, bool group, bool wide = false) {
+// kernel; wide: the 5-point one-solve kernel for IOP windows of 3 and 4;
+// march: the row-marching 5-point one-solve kernel.
+const void* kernel_for_bucket(const kiops_operator* op, int pb, bool group, bool wide = false, bool march = false) {
   const bool mixed = op->d.precision == KIOPS_MIXED;
   if (uses_3d(op)) return kernels_stencil3d(mixed, pb, group);
-  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) return kernels_stencil2d(mixed, pb, group, wide);
+  if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
+    if (march && !group) return kernels_stencil2d_march(mixed, pb);
+    return kernels_stencil2d(mixed, pb, group, wide);
+  }
   if (op->d.kind == KIOPS_OP_CSR) return kernels_csr(mixed, pb, group);
   return nullptr;
 }
 
-// The kernel instantiation that serves an operator, p and the IOP window q.
-const void* kernel_for(const kiops_operator* op, int p, int q = 2) {
-  return kernel_for_bucket(op, p_bucket(p), false, q == 3 || q == 4);
+// The one-solve kernel instantiation that serves an operator, p and the IOP window q.
+const void* kernel_for(const kiops_operator* op, int p, int q) {
+  return kernel_for_bucket(op, p_bucket(p), false, q == 3 || q == 4, use_march(op, q));
 }
 
-int64_t work_tiles(const kiops_operator* op) {
+// Work items of the pass: tiles (2-D tile pass), columns x z chunks (7-point
+// pass), strips x row chunks (2-D marching pass), row blocks (CSR).
+int64_t work_tiles(const kiops_operator* op, bool march = false) {
+  if (march) return march_items(op);
   if (uses_3d(op)) {
     using S = Stencil3D<double, 2>;
     const int64_t tx = (op->d.nx + S::TX - 1) / S::TX;
@@ -150,8 +180,8 @@ int64_t work_tiles(const kiops_operator* op) {
 }
 
 // Persistent grid: all workgroups co-resident, no more than the tiles of work.
-kiops_status grid_size(const kiops_operator* op, int p, int* nwg) {
-  const void* fn = kernel_for(op, p);
+kiops_status grid_size(const kiops_operator* op, int p, int q, int* nwg) {
+  const void* fn = kernel_for(op, p, q);
   if (!fn) return KIOPS_ERR_UNSUPPORTED;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess || per_cu < 1)
@@ -164,7 +194,7 @@ kiops_status grid_size(const kiops_operator* op, int p, int* nwg) {
   int64_t g = (int64_t)per_cu * op->cus;
   const char* ov = std::getenv("KIOPS_GRID");   // experiment override, capped by co-residency
   if (ov && std::atoi(ov) > 0) g = std::min<int64_t>(g, std::atoi(ov));
-  else g = std::min<int64_t>(g, std::max<int64_t>(1, work_tiles(op)));
+  else g = std::min<int64_t>(g, std::max<int64_t>(1, work_tiles(op, use_march(op, q))));
   *nwg = (int)g;
   return KIOPS_OK;
 }
@@ -260,6 +290,27 @@ Stencil2D<T, PB> make_stencil2d(const kiops_operator* op, int p, const double* c
     s.r_src = nullptr;
     s.r_dst = nullptr;
   }
+  return s;
+}
+
+template <typename T, int PB>
+Stencil2DMarch<T, PB> make_stencil2d_march(const kiops_operator* op, int p, const double* const* V, char* ws,
+                                           const Layout& L) {
+  const Stencil2D<T, PB> t = make_stencil2d<T, PB>(op, p, V, ws, L);   // coefficients and arrays
+  Stencil2DMarch<T, PB> s{};
+  s.N = t.N;
+  s.nx = t.nx;
+  s.ny = t.ny;
+  s.nstrips = (int)((op->d.nx + Stencil2DMarch<T, PB>::W - 1) / Stencil2DMarch<T, PB>::W);
+  s.nchunks = march_chunks(op);
+  s.nitems = s.nstrips * s.nchunks;
+  s.wE = t.wE; s.wW = t.wW; s.wN = t.wN; s.wS = t.wS; s.wC = t.wC;
+  s.r = t.r;
+  for (int c = 0; c < kPM; ++c) s.B[c] = t.B[c];
+  s.p = t.p;
+  s.r_src = t.r_src;
+  s.r_dst = t.r_dst;
+  s.ubuf = nullptr;
   return s;
 }
 
@@ -397,7 +448,7 @@ void stage_op(unsigned char* host_block, const OpT& o) {
 // Write the operator struct of the kernel instantiation for p-bucket pb
 // (pb >= p) into blk + 2048.
 kiops_status stage_op_block(const kiops_operator* op, int p, int pb, const double* const* V, char* ws,
-                            const Layout& L, unsigned char* blk) {
+                            const Layout& L, unsigned char* blk, bool march = false) {
   const bool mixed = op->d.precision == KIOPS_MIXED;
 #define KIOPS_STAGE(MAKE)                                                                          \
   switch (pb) {                                                                                    \
@@ -410,6 +461,8 @@ kiops_status stage_op_block(const kiops_operator* op, int p, int pb, const doubl
     KIOPS_STAGE(make_stencil3d)
   } else if (op->d.kind == KIOPS_OP_CSR) {
     KIOPS_STAGE(make_csr)
+  } else if (op->d.kind == KIOPS_OP_STENCIL2D_5PT && march) {
+    KIOPS_STAGE(make_stencil2d_march)
   } else if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
     KIOPS_STAGE(make_stencil2d)
   } else {
@@ -429,9 +482,8 @@ int op_family(const kiops_operator* op) {
 }
 
 // Launch one persistent solve and wait for its control block.
-kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, const double* const* V,
+kiops_status run_solve(kiops_operator* op, char* ws, const Layout& L, KParams& P, int p, const double* const* V,
                        Ctrl* host_ctrl, unsigned* host_abort) {
-  char* ws = reinterpret_cast<char*>(op->ws);
   hipLaunchKernelGGL(kiops_reset_kernel, dim3(1), dim3(256), 0, op->stream, P.bar, P.ctrl, P.arrive, L.nwg,
                      P.arrive_t);
   if (!hip_ok(hipGetLastError())) return KIOPS_ERR_DEVICE;
@@ -450,7 +502,7 @@ kiops_status run_solve(kiops_operator* op, const Layout& L, KParams& P, int p, c
   void* dOp = ws + L.params + 2048;
   const void* fn = kernel_for(op, p, P.q);
   if (!fn) return KIOPS_ERR_UNSUPPORTED;
-  kiops_status st = stage_op_block(op, p, p_bucket(p), V, ws, L, host_block);
+  kiops_status st = stage_op_block(op, p, p_bucket(p), V, ws, L, host_block, use_march(op, P.q));
   if (st != KIOPS_OK) return st;
   if (!hip_ok(hipMemcpyAsync(dP, host_block, sizeof(host_block), hipMemcpyHostToDevice, op->stream)))
     return KIOPS_ERR_DEVICE;
@@ -494,6 +546,7 @@ void fill_stats(const Ctrl& c, int nwg, double clock_hz, kiops_stats* st) {
   st->alg_bytes = c.alg_bytes;
   st->beta_last = c.beta;
   st->status = c.status;
+  st->m_max = c.m_max;
   st->time_reduce_s = (double)c.t_red / clock_hz;
   st->time_publish_s = (double)c.t_pub / clock_hz;
   st->time_serial_s = (double)c.t_ser / clock_hz;
@@ -1090,7 +1143,7 @@ kiops_status kiops_device_info(const kiops_operator* op, int* compute_units, int
   if (compute_units) *compute_units = op->cus;
   if (grid_blocks) {
     int g = 0;
-    kiops_status s = grid_size(op, 2, &g);
+    kiops_status s = grid_size(op, 2, 2, &g);
     if (s != KIOPS_OK) return s;
     *grid_blocks = g;
   }
@@ -1104,7 +1157,7 @@ kiops_status kiops_workspace_bytes(const kiops_operator* op, int p, int q, const
   resolve_options(op, opts, &m_min, &m_max, &max_sub);
   if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max) return KIOPS_ERR_INVALID_ARG;
   int nwg = 0;
-  kiops_status s = grid_size(op, p, &nwg);
+  kiops_status s = grid_size(op, p, q, &nwg);
   if (s != KIOPS_OK) return s;
   *bytes = make_layout(op, p, q, m_max, nwg).total;
   return KIOPS_OK;
@@ -1131,7 +1184,7 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
   resolve_options(op, opts, &m_min, &m_max, &max_sub);
   if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max || m_min < 1) return KIOPS_ERR_INVALID_ARG;
   if (q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
-  if (!kernel_for(op, p)) return KIOPS_ERR_UNSUPPORTED;
+  if (!kernel_for(op, p, q)) return KIOPS_ERR_UNSUPPORTED;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (tau == 0.0) {
     if (w != V[0] &&
@@ -1141,7 +1194,7 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
     return KIOPS_OK;
   }
   int nwg = 0;
-  s = grid_size(op, p, &nwg);
+  s = grid_size(op, p, q, &nwg);
   if (s != KIOPS_OK) return s;
   const Layout L = make_layout(op, p, q, m_max, nwg);
   if (!op->ws || op->ws_bytes < L.total) return KIOPS_ERR_OUT_OF_MEMORY;
@@ -1149,7 +1202,7 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
                           max_sub, kModeSolve, w);
   Ctrl hc{};
   unsigned abort_flag = 0;
-  s = run_solve(op, L, P, p, V, &hc, &abort_flag);
+  s = run_solve(op, reinterpret_cast<char*>(op->ws), L, P, p, V, &hc, &abort_flag);
   if (s != KIOPS_OK) return s;
   fill_stats(hc, nwg, (double)op->clock_hz, stats);
   if (abort_flag) return KIOPS_ERR_DEVICE;
@@ -1177,10 +1230,10 @@ kiops_status kiops_phi_combination_times(kiops_operator* op, int n, const double
   resolve_options(op, opts, &m_min, &m_max, &max_sub);
   if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max || m_min < 1) return KIOPS_ERR_INVALID_ARG;
   if (q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
-  if (!kernel_for(op, p)) return KIOPS_ERR_UNSUPPORTED;
+  if (!kernel_for(op, p, q)) return KIOPS_ERR_UNSUPPORTED;
   if (stats) std::memset(stats, 0, sizeof(*stats));
   int nwg = 0;
-  s = grid_size(op, p, &nwg);
+  s = grid_size(op, p, q, &nwg);
   if (s != KIOPS_OK) return s;
   const double T_end = times[n - 1];
   const Layout L = make_layout(op, p, q, m_max, nwg);
@@ -1195,7 +1248,7 @@ kiops_status kiops_phi_combination_times(kiops_operator* op, int n, const double
   }
   Ctrl hc{};
   unsigned abort_flag = 0;
-  s = run_solve(op, L, P, p, V, &hc, &abort_flag);
+  s = run_solve(op, reinterpret_cast<char*>(op->ws), L, P, p, V, &hc, &abort_flag);
   if (s != KIOPS_OK) return s;
   fill_stats(hc, nwg, (double)op->clock_hz, stats);
   if (abort_flag) return KIOPS_ERR_DEVICE;
@@ -1209,9 +1262,9 @@ kiops_status kiops_iop_basis(kiops_operator* op, int p, const double* const* V, 
   if (!V || p < 0 || p > KIOPS_P_MAX) return KIOPS_ERR_INVALID_ARG;
   for (int k = 0; k <= p; ++k)
     if (!V[k]) return KIOPS_ERR_INVALID_ARG;
-  if (!kernel_for(op, p)) return KIOPS_ERR_UNSUPPORTED;
+  if (!kernel_for(op, p, q)) return KIOPS_ERR_UNSUPPORTED;
   int nwg = 0;
-  kiops_status s = grid_size(op, p, &nwg);
+  kiops_status s = grid_size(op, p, q, &nwg);
   if (s != KIOPS_OK) return s;
   const Layout L = make_layout(op, p, q, m, nwg);
   // w holds b_0 during the run: place it in the last slot row of the workspace tail
@@ -1222,7 +1275,7 @@ kiops_status kiops_iop_basis(kiops_operator* op, int p, const double* const* V, 
   KParams P = make_params(op, L, ws, 1.0, p, V, 1.0, m, q, 1, m, 1, kModeBasis, wtmp);
   Ctrl hc{};
   unsigned abort_flag = 0;
-  s = run_solve(op, L, P, p, V, &hc, &abort_flag);
+  s = run_solve(op, reinterpret_cast<char*>(op->ws), L, P, p, V, &hc, &abort_flag);
   if (s != KIOPS_OK) return s;
   if (abort_flag) return KIOPS_ERR_DEVICE;
   if (hc.status != KIOPS_OK) return (kiops_status)hc.status;
