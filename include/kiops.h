@@ -175,6 +175,25 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
                                    double tol, int m_init, int q, const kiops_options* opts,
                                    double* w, kiops_stats* stats);
 
+/*
+ * kiops_phi_combination_noalloc: kiops_phi_combination with no allocation and
+ * no attached workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, results and errors as kiops_phi_combination;
+ * the solver's workspace is a fixed array inside the library, 128 MiB per
+ * GPU (one copy on every GPU the library runs on, held until the process
+ * ends).  A problem whose workspace (kiops_workspace_bytes) exceeds it
+ * returns KIOPS_ERR_OUT_OF_MEMORY and launches nothing: at the default
+ * m_max = 128 in FP64 that is N up to about 128000 (a 350^2 grid).  Calls no
+ * hipMalloc/hipFree; the control words the solve needs cleared are reset by
+ * a kernel at the start of every call.  Every call on one GPU uses the same
+ * array: calls that overlap on one GPU (other streams, other threads) race
+ * and must be serialised by the caller.
+ */
+kiops_status kiops_phi_combination_noalloc(kiops_operator* op, double tau, int p, const double* const* V,
+                                           double tol, int m_init, int q, const kiops_options* opts,
+                                           double* w, kiops_stats* stats);
+
 /* Several output times (Algorithm 1 with T = [T_1, ..., T_n] and Algorithm 3):
  * one adaptive integration from 0 to T_n = T_end that, at every accepted
  * substep containing output times T_k < T_now + tau, forms

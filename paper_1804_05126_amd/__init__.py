@@ -17,7 +17,7 @@ from typing import List, Optional, Sequence
 from . import _lib
 from ._lib import KiopsError  # noqa: F401
 
-__all__ = ["Operator", "phi_combination", "phi_batch", "batch_tune", "Server", "iop_basis", "small_expm",
+__all__ = ["Operator", "phi_combination", "phi_combination_noalloc", "phi_batch", "batch_tune", "Server", "iop_basis", "small_expm",
            "stream_probe", "controller_decide", "KiopsError"]
 
 
@@ -167,6 +167,24 @@ def phi_combination(op: Operator, tau: float, vectors: Sequence, tol: float = 1e
     if check:
         _lib.check(status, "kiops_phi_combination")
     return w, st.as_dict(), status
+
+
+def phi_combination_noalloc(op: Operator, tau: float, vectors: Sequence, out, tol: float = 1e-8,
+                            m_init: int = 10, q: int = 2, m_min: int = 0, m_max: int = 0,
+                            max_substeps: int = 0, check: bool = True):
+    """phi_combination through the entry point that allocates nothing (the
+    library's fixed scratch array is the workspace; the output buffer `out`
+    is the caller's).  Returns (out, stats dict, status)."""
+    p = len(vectors) - 1
+    V = _vec_ptrs(vectors, op.n)
+    _require_cuda_f64(out, op.n, "w")
+    o = _lib.Options(m_min, m_max, max_substeps, 0)
+    st = _lib.Stats()
+    status = op._lib.kiops_phi_combination_noalloc(op._h, float(tau), p, V, float(tol), int(m_init), int(q),
+                                                   C.byref(o), C.c_void_p(_ptr(out)), C.byref(st))
+    if check:
+        _lib.check(status, "kiops_phi_combination_noalloc")
+    return out, st.as_dict(), status
 
 
 def phi_combination_times(op: Operator, times: Sequence[float], vectors: Sequence, task: int = 2,

@@ -106,6 +106,9 @@ SIGNATURES = [
     ("kiops_phi_combination", C.c_int, [C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_void_p),
                                         C.c_double, C.c_int, C.c_int, C.POINTER(Options),
                                         C.c_void_p, C.POINTER(Stats)]),
+    ("kiops_phi_combination_noalloc", C.c_int, [C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_void_p),
+                                                C.c_double, C.c_int, C.c_int, C.POINTER(Options),
+                                                C.c_void_p, C.POINTER(Stats)]),
     ("kiops_phi_combination_times", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_int, C.c_int,
                                               C.POINTER(C.c_void_p), C.c_double, C.c_int, C.c_int,
                                               C.POINTER(Options), C.POINTER(C.c_void_p), C.POINTER(Stats)]),

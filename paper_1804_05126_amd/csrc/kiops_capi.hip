@@ -11,6 +11,7 @@
 #include <new>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
@@ -1069,6 +1070,85 @@ int reserve_gang(const kiops_server* s, int k) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- no-allocation scratch
+
+// Device memory of kiops_phi_combination_noalloc: a fixed array in the code
+// object, one copy per GPU the library runs on, held until the process ends.
+// In host code `scratch` names a host-side stand-in, never the device array:
+// its device address is taken once per device with hipGetSymbolAddress and
+// only that address is used.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mutex;
+char* scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on device dev (taken with dev current, once).
+kiops_status scratch_of_device(int dev, char** out) {
+  if (dev < 0 || dev >= kScratchDevices) return KIOPS_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    int cur = -1;
+    if (!hip_ok(hipGetDevice(&cur))) return KIOPS_ERR_DEVICE;
+    if (cur != dev && !hip_ok(hipSetDevice(dev))) return KIOPS_ERR_DEVICE;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) hipSetDevice(cur);
+    if (!hip_ok(e) || !ptr || reinterpret_cast<uintptr_t>(ptr) % kAlign != 0) return KIOPS_ERR_DEVICE;
+    scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = scratch_ptr[dev];
+  return KIOPS_OK;
+}
+
+// One solve with the operator's workspace (ws == nullptr) or with the given
+// device memory of ws_bytes (the no-allocation scratch).
+kiops_status phi_combination_in(kiops_operator* op, char* ws, size_t ws_bytes, double tau, int p,
+                                const double* const* V, double tol, int m_init, int q,
+                                const kiops_options* opts, double* w, kiops_stats* stats) {
+  if (!op) return KIOPS_ERR_INVALID_ARG;
+  if (!(tau >= 0.0) || !std::isfinite(tau) || !(tol > 0.0) || !std::isfinite(tol) || m_init < 1 ||
+      q < 0 || q > 8)
+    return KIOPS_ERR_INVALID_ARG;
+  kiops_status s = check_vectors(op, p, V, w);
+  if (s != KIOPS_OK) return s;
+  int m_min, m_max, max_sub;
+  resolve_options(op, opts, &m_min, &m_max, &max_sub);
+  if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max || m_min < 1) return KIOPS_ERR_INVALID_ARG;
+  if (q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
+  if (!kernel_for(op, p, q)) return KIOPS_ERR_UNSUPPORTED;
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (tau == 0.0) {
+    if (w != V[0] &&
+        !hip_ok(hipMemcpyAsync(w, V[0], sizeof(double) * op->N, hipMemcpyDeviceToDevice, op->stream)))
+      return KIOPS_ERR_DEVICE;
+    if (!hip_ok(hipStreamSynchronize(op->stream))) return KIOPS_ERR_DEVICE;
+    return KIOPS_OK;
+  }
+  int nwg = 0;
+  s = grid_size(op, p, q, &nwg);
+  if (s != KIOPS_OK) return s;
+  const Layout L = make_layout(op, p, q, m_max, nwg);
+  if (!ws) {
+    ws = reinterpret_cast<char*>(op->ws);
+    ws_bytes = op->ws_bytes;
+  }
+  if (!ws || ws_bytes < L.total) return KIOPS_ERR_OUT_OF_MEMORY;
+  KParams P = make_params(op, L, ws, tau, p, V, tol, m_init, q, m_min, m_max, max_sub, kModeSolve, w);
+  Ctrl hc{};
+  unsigned abort_flag = 0;
+  s = run_solve(op, ws, L, P, p, V, &hc, &abort_flag);
+  if (s != KIOPS_OK) return s;
+  fill_stats(hc, nwg, (double)op->clock_hz, stats);
+  if (abort_flag) return KIOPS_ERR_DEVICE;
+  return (kiops_status)hc.status;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* kiops_status_string(kiops_status s) {
@@ -1174,39 +1254,17 @@ kiops_status kiops_set_workspace(kiops_operator* op, void* dev_ptr, size_t bytes
 kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const double* const* V,
                                    double tol, int m_init, int q, const kiops_options* opts,
                                    double* w, kiops_stats* stats) {
+  return phi_combination_in(op, nullptr, 0, tau, p, V, tol, m_init, q, opts, w, stats);
+}
+
+kiops_status kiops_phi_combination_noalloc(kiops_operator* op, double tau, int p, const double* const* V,
+                                           double tol, int m_init, int q, const kiops_options* opts,
+                                           double* w, kiops_stats* stats) {
   if (!op) return KIOPS_ERR_INVALID_ARG;
-  if (!(tau >= 0.0) || !std::isfinite(tau) || !(tol > 0.0) || !std::isfinite(tol) || m_init < 1 ||
-      q < 0 || q > 8)
-    return KIOPS_ERR_INVALID_ARG;
-  kiops_status s = check_vectors(op, p, V, w);
+  char* ws = nullptr;
+  const kiops_status s = scratch_of_device(op->device, &ws);
   if (s != KIOPS_OK) return s;
-  int m_min, m_max, max_sub;
-  resolve_options(op, opts, &m_min, &m_max, &max_sub);
-  if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max || m_min < 1) return KIOPS_ERR_INVALID_ARG;
-  if (q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
-  if (!kernel_for(op, p, q)) return KIOPS_ERR_UNSUPPORTED;
-  if (stats) std::memset(stats, 0, sizeof(*stats));
-  if (tau == 0.0) {
-    if (w != V[0] &&
-        !hip_ok(hipMemcpyAsync(w, V[0], sizeof(double) * op->N, hipMemcpyDeviceToDevice, op->stream)))
-      return KIOPS_ERR_DEVICE;
-    if (!hip_ok(hipStreamSynchronize(op->stream))) return KIOPS_ERR_DEVICE;
-    return KIOPS_OK;
-  }
-  int nwg = 0;
-  s = grid_size(op, p, q, &nwg);
-  if (s != KIOPS_OK) return s;
-  const Layout L = make_layout(op, p, q, m_max, nwg);
-  if (!op->ws || op->ws_bytes < L.total) return KIOPS_ERR_OUT_OF_MEMORY;
-  KParams P = make_params(op, L, reinterpret_cast<char*>(op->ws), tau, p, V, tol, m_init, q, m_min, m_max,
-                          max_sub, kModeSolve, w);
-  Ctrl hc{};
-  unsigned abort_flag = 0;
-  s = run_solve(op, reinterpret_cast<char*>(op->ws), L, P, p, V, &hc, &abort_flag);
-  if (s != KIOPS_OK) return s;
-  fill_stats(hc, nwg, (double)op->clock_hz, stats);
-  if (abort_flag) return KIOPS_ERR_DEVICE;
-  return (kiops_status)hc.status;
+  return phi_combination_in(op, ws, kScratchBytes, tau, p, V, tol, m_init, q, opts, w, stats);
 }
 
 kiops_status kiops_phi_combination_times(kiops_operator* op, int n, const double* times, int task, int p,
