@@ -494,6 +494,8 @@ kiops_status run_solve(kiops_operator* op, char* ws, const Layout& L, KParams& P
   // workgroups per CU when the grid fills every CU evenly (the 7-point pass
   // deals more items to the workgroups placed first on a CU)
   P.ranks = (uses_3d(op) && L.nwg % op->cus == 0 && L.nwg / op->cus <= 4) ? L.nwg / op->cus : 1;
+  // the marching 5-point pass balances the two workgroups of a CU by wave priority
+  if (use_march(op, P.q) && L.nwg == 2 * op->cus) P.ranks = 2;
   const char* rk = std::getenv("KIOPS_RANKS");   // experiment override
   if (rk) P.ranks = std::max(1, std::min(4, std::atoi(rk)));
   alignas(256) unsigned char host_block[4096];

@@ -116,6 +116,16 @@ struct Stencil2DMarch {
     const int nloc = (vgrid() - band + nband - 1) / nband;
     const int i_lo = (int)((int64_t)nitems * band / nband);
     const int i_hi = (int)((int64_t)nitems * (band + 1) / nband);
+    // Two workgroups per CU (c.ranks == 2): the second half of the grid is
+    // dispatched second onto every CU, and the SIMD arbitration favours the
+    // older waves, so with equal priority the second workgroup of a CU fell
+    // far behind the first (measured at 2048^2: 52 against 67 us per pass).
+    // The later workgroup runs at a raised wave priority for the first third
+    // of its rows, the earlier one for the other two thirds: both then arrive
+    // together (55 and 55 us, the latest arrival 59 instead of 75 us).
+    const bool two_per_cu = c.ranks == 2;
+    const bool late = two_per_cu && vblock() >= vgrid() / 2;
+    if (late) __builtin_amdgcn_s_setprio(1);
     for (int item = i_lo + vblock() / nband; item < i_hi; item += nloc) {
       const int strip = item / nchunks;
       const int chunk = item - strip * nchunks;
@@ -242,6 +252,10 @@ struct Stencil2DMarch {
       T hist0 = T(0), hist1 = T(0), r_out = T(0), bc_out = T(0);
       auto process = [&](int j, const RowLoads& L) {
         const int m = j + 1;   // formation row
+        if (two_per_cu && j == nrows / 3) {
+          if (late) __builtin_amdgcn_s_setprio(0);
+          else __builtin_amdgcn_s_setprio(1);
+        }
         T* Rb = sR + slot(m - 1) * kRowR;
         T* Rc = sR + slot(m) * kRowR;
         T* Ra = sR + slot(m + 1) * kRowR;
@@ -313,6 +327,7 @@ struct Stencil2DMarch {
       }
       __syncthreads();   // the rings and halo buffers are reused by the next item
     }
+    if (two_per_cu) __builtin_amdgcn_s_setprio(0);
   }
 };
 

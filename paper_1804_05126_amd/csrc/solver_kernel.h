@@ -80,8 +80,12 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
   if (vblock() != 0) {
     if (threadIdx.x == 0) {
       if (P.profile) P.arrive_t[vblock()] = (uint64_t)wall_clock64();
-      __threadfence();
-      __hip_atomic_store(&P.arrive[vblock()], epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
+      // release (the workgroup's stores, ordered before this thread by the
+      // barrier above) then the arrival flag; acquire after the release word.
+      // One-sided fences: a full fence would also invalidate the XCD's L2
+      // under the workgroups still running their pass.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&P.arrive[vblock()], epoch, __ATOMIC_RELAXED, KIOPS_AGENT);
       const uint64_t t0 = (uint64_t)wall_clock64();
       for (unsigned spins = 1;; ++spins) {
         if (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) break;
@@ -89,7 +93,7 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
         if ((spins & 63u) == 0 && spin_expired(b, t0, P.spin_limit)) break;
       }
       if (P.profile) P.arrive_t[P.nwg + vblock()] = (uint64_t)wall_clock64();
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     return;
@@ -107,7 +111,7 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
       if (S.expired) break;
     }
   }
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   __syncthreads();
   const uint64_t t1 = (uint64_t)wall_clock64();
   if (P.profile) {
@@ -159,8 +163,7 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
     __syncthreads();
   }
   epi();
-  __threadfence();
-  __syncthreads();
+  __syncthreads();   // the epilogue's stores (control block) before thread 0's release
   if (threadIdx.x == 0) {
     const uint64_t t2 = (uint64_t)wall_clock64();
     Ctrl& C = S.C;
@@ -168,20 +171,22 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
     C.t_wait += t1 - t0;
     C.t_epi += t2 - t1;
     C.t_last = t2;
-    P.ctrl->t_work = C.t_work;
-    P.ctrl->t_wait = C.t_wait;
-    P.ctrl->t_epi = C.t_epi;
-    P.ctrl->t_expm = C.t_expm;
-    P.ctrl->t_arrive_max = C.t_arrive_max;
-    P.ctrl->t_arrive_mean = C.t_arrive_mean;
-    P.ctrl->t_release_max = C.t_release_max;
-    P.ctrl->t_release_mean = C.t_release_mean;
-    P.ctrl->n_barriers = C.n_barriers;
-    P.ctrl->t_red = C.t_red;
-    P.ctrl->t_pub = C.t_pub;
-    P.ctrl->t_ser = C.t_ser;
-    __threadfence();
-    __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
+    if (P.profile || C.phase == kPhaseDone) {   // the timers the host reads at the end
+      P.ctrl->t_work = C.t_work;
+      P.ctrl->t_wait = C.t_wait;
+      P.ctrl->t_epi = C.t_epi;
+      P.ctrl->t_expm = C.t_expm;
+      P.ctrl->t_arrive_max = C.t_arrive_max;
+      P.ctrl->t_arrive_mean = C.t_arrive_mean;
+      P.ctrl->t_release_max = C.t_release_max;
+      P.ctrl->t_release_mean = C.t_release_mean;
+      P.ctrl->n_barriers = C.n_barriers;
+      P.ctrl->t_red = C.t_red;
+      P.ctrl->t_pub = C.t_pub;
+      P.ctrl->t_ser = C.t_ser;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELAXED, KIOPS_AGENT);
   }
   __syncthreads();
 }
@@ -197,15 +202,15 @@ __device__ inline void sub_barrier(const KParams& P, SmallState& S, unsigned& ep
   __syncthreads();
   if (vblock() != 0) {
     if (threadIdx.x == 0) {
-      __threadfence();
-      __hip_atomic_store(&P.arrive[vblock()], epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&P.arrive[vblock()], epoch, __ATOMIC_RELAXED, KIOPS_AGENT);
       const uint64_t t0 = (uint64_t)wall_clock64();
       for (unsigned spins = 1;; ++spins) {
         if (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) break;
         for (int z = 0; z < P.poll_sleep; ++z) __builtin_amdgcn_s_sleep(2);
         if ((spins & 63u) == 0 && spin_expired(b, t0, P.spin_limit)) break;
       }
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
     return;
@@ -223,9 +228,12 @@ __device__ inline void sub_barrier(const KParams& P, SmallState& S, unsigned& ep
       if (S.expired) break;
     }
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELEASE, KIOPS_AGENT);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();   // this workgroup's stage stores before thread 0's release
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELAXED, KIOPS_AGENT);
+  }
   __syncthreads();
 }
 
