@@ -51,6 +51,13 @@ def parse():
     ap.add_argument("--serve-lams", type=str, default="100,1000,5000", help="arrival rates, req/s (serve)")
     ap.add_argument("--serve-group", type=int, default=16, help="workgroups per server group (serve)")
     ap.add_argument("--serve-pool-gb", type=float, default=64.0, help="HBM budget of the server (serve)")
+    ap.add_argument("--traffic-from", type=str, default="", metavar="FETCH_CSV,WRITE_CSV",
+                    help="no GPU work: turn the rocprofv3 counter files of two bench runs (--pmc FETCH_SIZE, "
+                         "--pmc WRITE_SIZE, each with --calibrate-copy) into the traffic record --traffic-out")
+    ap.add_argument("--traffic-key", type=str, default="", help="workload key of the traffic record")
+    ap.add_argument("--traffic-out", type=str, default="", help="traffic record to write (JSON)")
+    ap.add_argument("--print-maps", action="store_true",
+                    help="print /proc/self/maps to stderr at exit (to resolve addresses of a crash in teardown)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run one plain device copy of MIB MiB (a known-size "
                          "kernel that HBM traffic counters are scaled by)")
@@ -125,6 +132,11 @@ def cpu_baseline(pr_sample, sweep_taus, one_thread_substeps):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        return _write_traffic(args)
+    if args.print_maps:
+        import atexit
+        atexit.register(lambda: sys.stderr.write(open("/proc/self/maps").read()))
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
@@ -157,7 +169,6 @@ def main():
     tol = 1e-8 if args.precision == "fp64" else 1e-6
     stream = torch.cuda.current_stream()
     elem = "double" if args.precision == "fp64" else "float"
-    kname = "Stencil2D" if args.q in (1, 2) else ("Stencil2DWide" if args.q in (3, 4) else "Stencil2D (full window)")
 
     def one_solve(tau):
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -225,7 +236,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": f"kiops_solve_kernel<{kname}<{elem}>, {elem}> (one persistent launch per solve)",
+            "kernel": (f"kiops_solve_kernel<{K._lib.PASS_NAMES.get(records[0][3]['pass_kind'], '?')}<{elem}>, {elem}> "
+                       f"(one persistent launch per solve)"),
             "algorithmic_bytes_per_launch": total_bytes / n_solves,
             "avg_launch_ms": total_ms / n_solves,
         },
@@ -234,6 +246,11 @@ def main():
         "per_tau": per_tau,
     }
     _calibrate_copy(args, torch, out)
+    # release the device objects before the host-side baseline and the exit
+    torch.cuda.synchronize()
+    op.close()
+    del op, vecs, w
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         sample = W.cfg2(side, taus[0], q=args.q)
         print("[bench] timing the CPU oracle (one whole solve)", file=sys.stderr, flush=True)
@@ -256,6 +273,56 @@ def _calibrate_copy(args, torch, out):
     torch.cuda.synchronize()
     out["copy_calibration_bytes"] = nbytes
     del src, dst
+
+
+def traffic_from_counters(fetch_csv, write_csv, key, out_path, kernel="kiops_solve_kernel"):
+    """HBM bytes per launch of the solve kernel from two rocprofv3 counter runs.
+
+    FETCH_SIZE and WRITE_SIZE (kilobytes per dispatch) of every dispatch whose
+    name contains `kernel` are scaled by what the same counter reads for the
+    calibration copy of the run (the library's streaming kernel, which reads
+    and writes a known number of bytes: --calibrate-copy) and averaged over
+    the launches.  Writes a record keyed by the workload and the current
+    kernel sources, which the bench then reports as roofline.traffic."""
+    import csv
+
+    def per_dispatch(path, counter):
+        rows = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = (r["Dispatch_Id"], r["Kernel_Name"])
+            rows[k] = rows.get(k, 0.0) + float(r["Counter_Value"])
+        return rows
+
+    out = {"workload_key": key, "kernel_source_hash": _kernel_hash(), "counters": {}}
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = per_dispatch(path, name)
+        calib = [v for (d, n), v in rows.items() if "stream_probe_kernel" in n]
+        launches = [v for (d, n), v in sorted(rows.items(), key=lambda x: int(x[0][0])) if kernel in n]
+        if len(calib) != 1 or not launches:
+            raise RuntimeError(f"{path}: need one calibration copy and the solve launches")
+        # the copy moves copy_bytes in each direction; the counter reads kilobytes
+        out["counters"][name] = {"calibration_kib": calib[0], "launch_kib": launches}
+    return out
+
+
+def _write_traffic(args):
+    fetch_csv, write_csv = args.traffic_from.split(",")
+    rec = traffic_from_counters(fetch_csv, write_csv, args.traffic_key, args.traffic_out)
+    copy_bytes = float(args.calibrate_copy << 20)
+    f = rec["counters"]["FETCH_SIZE"]
+    w = rec["counters"]["WRITE_SIZE"]
+    fetch_scale = copy_bytes / (f["calibration_kib"] * 1024.0)
+    write_scale = copy_bytes / (w["calibration_kib"] * 1024.0)
+    fb = [v * 1024.0 * fetch_scale for v in f["launch_kib"]]
+    wb = [v * 1024.0 * write_scale for v in w["launch_kib"]]
+    rec.update(fetch_scale=fetch_scale, write_scale=write_scale, launches=len(fb),
+               fetch_bytes_per_launch=sum(fb) / len(fb), write_bytes_per_launch=sum(wb) / len(wb),
+               hbm_bytes_per_launch=(sum(fb) + sum(wb)) / len(fb),
+               per_launch_GB=[(a + b) / 1e9 for a, b in zip(fb, wb)])
+    json.dump(rec, open(args.traffic_out, "w"), indent=1)
+    print(json.dumps({k: rec[k] for k in ("workload_key", "hbm_bytes_per_launch", "fetch_scale", "write_scale")}))
 
 
 def _traffic(path, key):

@@ -135,7 +135,16 @@ typedef struct {
   double time_reduce_s;    /* reductions of the per-workgroup partial sums */
   double time_publish_s;   /* copies of the control block */
   double time_serial_s;    /* normalisation, H column and next coefficients (thread 0) */
+  int32_t pass_kind;       /* the pass that ran: KIOPS_PASS_* */
+  int32_t reserved3;
 } kiops_stats;
+
+/* kiops_stats.pass_kind */
+#define KIOPS_PASS_TILE2D 0    /* 5-point tile pass (64 x 16 tiles) */
+#define KIOPS_PASS_WIDE2D 1    /* 5-point tile pass for IOP windows of 3 and 4 */
+#define KIOPS_PASS_MARCH2D 2   /* 5-point row-marching pass (large 2-D grids, windows of 1 and 2) */
+#define KIOPS_PASS_7PT 3       /* 7-point marching pass (3-D, and 2-D with a diffusivity field) */
+#define KIOPS_PASS_CSR 4       /* general sparse matrix */
 
 typedef struct kiops_operator kiops_operator;
 

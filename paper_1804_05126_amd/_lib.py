@@ -32,6 +32,7 @@ MIXED = 1
 M_MAX_LIMIT = 128
 P_MAX = 8
 EXPM_SCRATCH_DOUBLES = 9 * 144 * 144
+PASS_NAMES = {0: "Stencil2D", 1: "Stencil2DWide", 2: "Stencil2DMarch", 3: "Stencil3D", 4: "CsrOp"}
 
 
 class OperatorDesc(C.Structure):
@@ -67,6 +68,7 @@ class Stats(C.Structure):
         ("release_max_s", C.c_double), ("release_mean_s", C.c_double),
         ("status", C.c_int32), ("m_max", C.c_int32),
         ("time_reduce_s", C.c_double), ("time_publish_s", C.c_double), ("time_serial_s", C.c_double),
+        ("pass_kind", C.c_int32), ("reserved3", C.c_int32),
     ]
 
     def as_dict(self) -> dict:

@@ -141,6 +141,14 @@ bool use_march(const kiops_operator* op, int q) {
   return op->d.nx >= Stencil2DMarch<double, 2>::W && march_items(op) >= op->cus;
 }
 
+// The pass a one-solve kernel runs for this operator and window (KIOPS_PASS_*).
+int pass_kind(const kiops_operator* op, int q) {
+  if (uses_3d(op)) return KIOPS_PASS_7PT;
+  if (op->d.kind == KIOPS_OP_CSR) return KIOPS_PASS_CSR;
+  if (use_march(op, q)) return KIOPS_PASS_MARCH2D;
+  return (q == 3 || q == 4) ? KIOPS_PASS_WIDE2D : KIOPS_PASS_TILE2D;
+}
+
 // Kernel of an operator for p-bucket pb: the one-solve kernel or the group
 // kernel; wide: the 5-point one-solve kernel for IOP windows of 3 and 4;
 // march: the row-marching 5-point one-solve kernel.
@@ -1145,6 +1153,7 @@ kiops_status phi_combination_in(kiops_operator* op, char* ws, size_t ws_bytes, d
   s = run_solve(op, ws, L, P, p, V, &hc, &abort_flag);
   if (s != KIOPS_OK) return s;
   fill_stats(hc, nwg, (double)op->clock_hz, stats);
+  if (stats) stats->pass_kind = pass_kind(op, q);
   if (abort_flag) return KIOPS_ERR_DEVICE;
   return (kiops_status)hc.status;
 }
@@ -1311,6 +1320,7 @@ kiops_status kiops_phi_combination_times(kiops_operator* op, int n, const double
   s = run_solve(op, reinterpret_cast<char*>(op->ws), L, P, p, V, &hc, &abort_flag);
   if (s != KIOPS_OK) return s;
   fill_stats(hc, nwg, (double)op->clock_hz, stats);
+  if (stats) stats->pass_kind = pass_kind(op, q);
   if (abort_flag) return KIOPS_ERR_DEVICE;
   return (kiops_status)hc.status;
 }
