@@ -8,7 +8,7 @@ namespace kiops {
 
 const void* kernels_stencil2d(bool mixed, int pb, bool group, bool wide);   // wide: IOP windows of 3, 4 (one-solve kernel)
 const void* kernels_stencil2d_march(bool mixed, int pb);   // row-marching 5-point pass (one-solve kernel)
-const void* kernels_stencil3d(bool mixed, int pb, bool group);
+const void* kernels_stencil3d(bool mixed, int pb, bool group, bool narrow);   // narrow: IOP windows of 1, 2 (one-solve kernel)
 const void* kernels_csr(bool mixed, int pb, bool group);
 const void* kernels_serve();   // served form: 2-D and 3-D stencils, FP64 and mixed, p <= 4
 

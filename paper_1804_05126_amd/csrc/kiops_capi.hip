@@ -151,10 +151,12 @@ int pass_kind(const kiops_operator* op, int q) {
 
 // Kernel of an operator for p-bucket pb: the one-solve kernel or the group
 // kernel; wide: the 5-point one-solve kernel for IOP windows of 3 and 4;
-// march: the row-marching 5-point one-solve kernel.
-const void* kernel_for_bucket(const kiops_operator* op, int pb, bool group, bool wide = false, bool march = false) {
+// march: the row-marching 5-point one-solve kernel; narrow: the 7-point
+// one-solve kernel for IOP windows of 1 and 2.
+const void* kernel_for_bucket(const kiops_operator* op, int pb, bool group, bool wide = false, bool march = false,
+                              bool narrow = false) {
   const bool mixed = op->d.precision == KIOPS_MIXED;
-  if (uses_3d(op)) return kernels_stencil3d(mixed, pb, group);
+  if (uses_3d(op)) return kernels_stencil3d(mixed, pb, group, narrow);
   if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
     if (march && !group) return kernels_stencil2d_march(mixed, pb);
     return kernels_stencil2d(mixed, pb, group, wide);
@@ -165,7 +167,7 @@ const void* kernel_for_bucket(const kiops_operator* op, int pb, bool group, bool
 
 // The one-solve kernel instantiation that serves an operator, p and the IOP window q.
 const void* kernel_for(const kiops_operator* op, int p, int q) {
-  return kernel_for_bucket(op, p_bucket(p), false, q == 3 || q == 4, use_march(op, q));
+  return kernel_for_bucket(op, p_bucket(p), false, q == 3 || q == 4, use_march(op, q), q == 1 || q == 2);
 }
 
 // Work items of the pass: tiles (2-D tile pass), columns x z chunks (7-point

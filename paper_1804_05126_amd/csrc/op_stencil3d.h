@@ -28,8 +28,13 @@
 
 namespace kiops {
 
-template <typename T, int PB>
-struct Stencil3D {
+// kNarrow: the one-solve instantiation for IOP windows of one or two vectors
+// (q = 1, 2), whose formation reads no vector older than R_{kp-2} and whose
+// inner products take R_{kp-1} alone (from LDS); a separate kernel, since the
+// branches that load older vectors, present in the same code, cost the common
+// window 4% at 256^3 (measured).
+template <typename T, int PB, bool kNarrow>
+struct Stencil3DT {
   static constexpr int TX = 32, TY = 8;
   static_assert(TX * TY == kThreads && (TX & (TX - 1)) == 0, "one tile position per thread");
   static constexpr int RX = TX + 4, RY = TY + 4, RP = RX * RY;   // halo-2 plane (R_{kp-1}, kappa)
@@ -39,7 +44,8 @@ struct Stencil3D {
   static constexpr int kLdsT = 3 * RP + 4 * RP + 3 * SP;         // elements of T
   static constexpr int kLdsDoubles = (int)((kLdsT * sizeof(T) + 7) / 8);
   static constexpr bool kTwoPhase = false;   // one fused pass per Krylov step
-  static constexpr int kWavesPerEU = 3;
+  static constexpr int kWavesPerEU = sizeof(T) == 4 ? 3 : 3;
+  static constexpr int kDepth = 3;   // FP32: plane steps whose loads are in flight at a time
 
   struct PlaneLoads {
     T vr[kRegionLoads], vk[kRegionLoads];   // halo-2 plane of R_{kp-1} and kappa
@@ -82,6 +88,15 @@ struct Stencil3D {
     rx = TX; ry = e;
   }
 
+  // z mod n for z in [-2n, 3n), without a branch (wave-uniform planes)
+  __device__ static int wrap_plane(int z, int n) {
+    z = z < 0 ? z + n : z;
+    z = z < 0 ? z + n : z;
+    z = z >= n ? z - n : z;
+    z = z >= n ? z - n : z;
+    return z;
+  }
+
   // stencil of field u at the centre c, diffusivities at the centre and the six
   // neighbours, face diffusivity written as (kc + kn) * half_h2inv
   __device__ T apply(T c, T xp, T xm, T yp, T ym, T zp, T zm, T kc, T kxp, T kxm, T kyp, T kym,
@@ -115,6 +130,9 @@ struct Stencil3D {
     const __amdgpu_buffer_rsrc_t rsR = make_rsrc(first ? nullptr : bp.get(c.src), nb);
     const __amdgpu_buffer_rsrc_t rsO = make_rsrc(has_old ? bp.get(c.src - 1) : nullptr, nb);
     const __amdgpu_buffer_rsrc_t rsW = make_rsrc(first ? w : nullptr, (uint64_t)N * 8);
+    // FP64: the formation's second vector is w in the first pass, else R_{kp-2}
+    const __amdgpu_buffer_rsrc_t rsOW =
+        make_rsrc(first ? (const void*)w : (has_old ? (const void*)bp.get(c.src - 1) : nullptr), nb);
     const __amdgpu_buffer_rsrc_t rsr = make_rsrc(r, nb);
     const __amdgpu_buffer_rsrc_t rsK = make_rsrc(kappa, nb);
     const __amdgpu_buffer_rsrc_t rsOut = make_rsrc(c.write_out ? Rout : nullptr, nb);
@@ -198,8 +216,8 @@ struct Stencil3D {
         pin[q] = (q == 0) || ring;
         poff[q] = (uint32_t)(wrap_index(y0 + pry[q], ny) * nx + wrap_index(x0 + prx[q], nx));
       }
-      auto region_load = [&](int zz, T* vr, T* vk) {
-        const uint32_t zo = (uint32_t)(wrap_index(zz, nz) * plane);
+      auto region_load = [&](int zz, T* vr, T* vk) __attribute__((always_inline)) {
+        const uint32_t zo = (uint32_t)(wrap_plane(zz, nz) * plane);
 #pragma unroll
         for (int i = 0; i < kRegionLoads; ++i) {
           const uint32_t o = rin[i] ? (zo + roff[i]) * (uint32_t)sizeof(T) : kNoOffset;
@@ -207,7 +225,7 @@ struct Stencil3D {
           vk[i] = buf_ld(rsK, o, T(0));
         }
       };
-      auto region_store = [&](int slot_r, int slot_k, const T* vr, const T* vk) {
+      auto region_store = [&](int slot_r, int slot_k, const T* vr, const T* vk) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < kRegionLoads; ++i) {
           const int e = t + i * kThreads;
@@ -228,20 +246,27 @@ struct Stencil3D {
       T rv_prev = T(0), bc_prev = T(0);
       // every global load of plane step zf: plane zf+1 of R_{kp-1} and kappa,
       // and r, the older window vector and B at the thread's positions of plane zf
-      auto issue = [&](int zf, PlaneLoads& L) {
+      auto issue = [&](int zf, PlaneLoads& L) __attribute__((always_inline)) {
         region_load(zf + 1, L.vr, L.vk);
-        const uint32_t zo = (uint32_t)(wrap_index(zf, nz) * plane);
+        const uint32_t zo = (uint32_t)(wrap_plane(zf, nz) * plane);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           L.goff[q] = pin[q] ? (zo + poff[q]) * (uint32_t)sizeof(T) : kNoOffset;
           L.rv[q] = buf_ld(rsr, L.goff[q], T(0));
-          if (first) L.ov[q] = (T)buf_ld(rsW, pin[q] ? (zo + poff[q]) * 8u : kNoOffset, 0.0);
-          else L.ov[q] = buf_ld(rsO, L.goff[q], T(0));
+          if constexpr (sizeof(T) == 8) {
+            L.ov[q] = buf_ld(rsOW, L.goff[q], T(0));   // w (first pass) or R_{kp-2}: one load, no branch
+          } else {
+            // mixed: w is FP64, R_{kp-2} FP32; both loads are issued (one of
+            // the two resources is empty) so that no branch separates them
+            const double w0 = buf_ld(rsW, pin[q] ? (zo + poff[q]) * 8u : kNoOffset, 0.0);
+            const T o0 = buf_ld(rsO, L.goff[q], T(0));
+            L.ov[q] = first ? (T)w0 : o0;
+          }
 #pragma unroll
           for (int k = 0; k < PB; ++k) L.bv[q][k] = buf_ld(rsB[k], L.goff[q], T(0));
         }
       };
-      auto process = [&](int zf, const PlaneLoads& L) {
+      auto process = [&](int zf, const PlaneLoads& L) __attribute__((always_inline)) {
         const int lz = zf - (z0 - 2);             // >= 1
         const int sr_m = (lz - 1) % 3, sr_c = lz % 3, sr_p = (lz + 1) % 3;
         const int sk_m2 = (lz + 2) % 4, sk_m = (lz + 3) % 4, sk_c = lz % 4, sk_p = (lz + 1) % 4;
@@ -275,7 +300,7 @@ struct Stencil3D {
               X = c.a * U;
               X = fma(c.bw[c.src], ctr, X);
               if (has_old) X = fma(c.bw[c.src - 1], L.ov[q], X);
-              if (more_old) {
+              if (!kNarrow && more_old) {
                 // older window vectors (a full window streams every earlier
                 // vector: eight loads in flight at a time)
                 int i = c.flo;
@@ -305,7 +330,7 @@ struct Stencil3D {
                       sK[sk_c * RP + o2], sK[sk_m2 * RP + o2], rv_prev);
           U += bc_prev;
           const bool valid = (x0 + tcx < nx) && (y0 + tcy < ny);
-          const uint32_t zo1 = (uint32_t)(wrap_index(zf - 1, nz) * plane);
+          const uint32_t zo1 = (uint32_t)(wrap_plane(zf - 1, nz) * plane);
           const uint32_t off1 = (zo1 + poff[0]) * (uint32_t)sizeof(T);
           buf_st(rsOut, valid ? off1 : kNoOffset, X);
           if (store_u) buf_st(rsU, valid ? off1 : kNoOffset, U);
@@ -313,14 +338,23 @@ struct Stencil3D {
           acc.RR = fma(Xd, Xd, acc.RR);
           acc.UU = fma(Ud, Ud, acc.UU);
           acc.Ck = fma(Xd, Ud, acc.Ck);
+          // inner products with the window [dlo, kp-1]: R_{kp-1} is in LDS,
+          // older vectors (windows of three or more) are loaded here
+          const double Rs = (double)sR[sr_m * RP + o2];
+          if constexpr (kNarrow) {
+            if (c.ngd > 0) {
+              acc.G[0] = fma(Rs, Xd, acc.G[0]);
+              acc.C[0] = fma(Rs, Ud, acc.C[0]);
+            }
+          } else {
 #pragma unroll
-          for (int d = 0; d < kWinMax - 1; ++d) {
-            if (d < c.ngd) {
-              const int idx = c.dlo + d;
-              const double Rv = (idx == c.src) ? (double)sR[sr_m * RP + o2]
-                                               : (double)buf_ld(make_rsrc(bp.get(idx), nb), off1, T(0));
-              acc.G[d] = fma(Rv, Xd, acc.G[d]);
-              acc.C[d] = fma(Rv, Ud, acc.C[d]);
+            for (int d = 0; d < kWinMax - 1; ++d) {
+              if (d < c.ngd) {
+                const int idx = c.dlo + d;
+                const double Rv = (idx == c.src) ? Rs : (double)buf_ld(make_rsrc(bp.get(idx), nb), off1, T(0));
+                acc.G[d] = fma(Rv, Xd, acc.G[d]);
+                acc.C[d] = fma(Rv, Ud, acc.C[d]);
+              }
             }
           }
         }
@@ -328,27 +362,30 @@ struct Stencil3D {
         rv_prev = L.rv[0];
         bc_prev = bc_cur;
       };
+      // plane steps zf = z0 - 1 .. z1
       if constexpr (sizeof(T) == 4) {
         // three register sets rotate so that the loads of the next two plane
-        // steps are in flight while the current one is processed (FP32 data
-        // leaves the registers for it; with FP64 the third set spills and
-        // costs 14%, measured at 256^3)
-        PlaneLoads la, lb, lc;
-        issue(z0 - 1, la);
-        if (z0 <= z1) issue(z0, lb);
-        for (int zf = z0 - 1; zf <= z1; zf += 3) {
-          if (zf + 2 <= z1) issue(zf + 2, lc);
-          process(zf, la);
-          if (zf + 1 > z1) break;
-          if (zf + 3 <= z1) issue(zf + 3, la);
-          process(zf + 1, lb);
-          if (zf + 2 > z1) break;
-          if (zf + 4 <= z1) issue(zf + 4, lb);
-          process(zf + 2, lc);
+        // steps are in flight while the current one is processed; the issues
+        // are unconditional (past the chunk they repeat its last plane,
+        // served by the caches), so that no branch separates a load from the
+        // wait that counts it and each wait leaves the later steps' loads in
+        // flight
+        PlaneLoads Ls[kDepth];
+#pragma unroll
+        for (int u = 0; u < kDepth - 1; ++u) issue(z0 - 1 + u < z1 ? z0 - 1 + u : z1, Ls[u]);
+        for (int zb = z0 - 1; zb <= z1; zb += kDepth) {
+#pragma unroll
+          for (int u = 0; u < kDepth; ++u) {
+            const int za = zb + u + kDepth - 1;
+            issue(za < z1 ? za : z1, Ls[(u + kDepth - 1) % kDepth]);
+            if (zb + u <= z1) process(zb + u, Ls[u]);
+          }
         }
       } else {
         // two register sets alternate so that the loads of the next plane
-        // step are in flight while the current one is processed
+        // step are in flight while the current one is processed (the FP64
+        // sets leave no room for a third at three waves per SIMD; the
+        // unconditional issue of the FP32 loop measured no faster here)
         PlaneLoads la, lb;
         issue(z0 - 1, la);
         for (int zf = z0 - 1; zf <= z1; zf += 2) {
@@ -362,5 +399,10 @@ struct Stencil3D {
     }
   }
 };
+
+template <typename T, int PB>
+using Stencil3D = Stencil3DT<T, PB, false>;
+template <typename T, int PB>
+using Stencil3DNarrow = Stencil3DT<T, PB, true>;
 
 }  // namespace kiops
