@@ -43,9 +43,11 @@ def parse():
     ap.add_argument("--cpu-sample-substeps", type=int, default=1,
                     help="substeps of the one-thread CPU oracle sample")
     ap.add_argument("--traffic-json", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--workload", choices=("adr2d", "diff3d", "batch", "serve", "small"), default="adr2d",
+    ap.add_argument("--workload", choices=("adr2d", "diff3d", "batch", "serve", "small", "probe"), default="adr2d",
                     help="adr2d: the 2048^2 tau sweep (default); diff3d: the 256^3 variable-"
-                         "coefficient solve; batch: 256 2-D problems in one launch vs a per-solve loop")
+                         "coefficient solve; batch: 256 2-D problems in one launch vs a per-solve loop; "
+                         "probe: the streaming ceiling of the device (the library's plain streaming kernel)")
+    ap.add_argument("--probe-mib", type=int, default=1024, help="MiB per array (probe)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-count", type=int, default=48, help="requests per arrival rate (serve)")
     ap.add_argument("--serve-lams", type=str, default="100,1000,5000", help="arrival rates, req/s (serve)")
@@ -159,6 +161,8 @@ def main():
         return 2
     if args.workload == "small":
         return bench_small(args, W, K, np, torch)
+    if args.workload == "probe":
+        return bench_probe(args, K, torch)
     taus = [float(t) for t in args.taus.split(",")] if args.taus else W.cfg2_tau_grid()
     side = args.side
     pr = W.cfg2(side, taus[0], q=args.q)       # operator and vectors shared by the sweep
@@ -256,6 +260,46 @@ def main():
         print("[bench] timing the CPU oracle (one whole solve)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sample, taus, args.cpu_sample_substeps)
     print(json.dumps(out), flush=True)
+
+
+def bench_probe(args, K, torch):
+    """Streaming ceiling: dst = src_0 + ... + src_{r-1} over arrays of
+    --probe-mib MiB by the library's plain streaming kernel (16-byte loads),
+    for r = 1 (a copy), 2, 4 and 6 reads per write (the 5-point pass streams
+    about six arrays per one written) and three grid sizes; HIP events on the
+    launch stream, best grid per r."""
+    n = (args.probe_mib << 20) // 8
+    srcs = [torch.full((n,), 1.0 + k, dtype=torch.float64, device="cuda") for k in range(6)]
+    dst = torch.empty(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for r in (1, 2, 4, 6):
+        best = None
+        for blocks in (512, 1024, 2048, 4096):
+            for _ in range(2):
+                K.stream_probe(srcs[:r], dst, blocks=blocks)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = max(1, args.steps) * 5
+            e0.record(stream)
+            for _ in range(reps):
+                K.stream_probe(srcs[:r], dst, blocks=blocks)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = (r + 1) * n * 8 / (ms * 1e-3) / 1e9
+            rows.append({"reads": r, "blocks": blocks, "us": ms * 1e3, "GB_s": gbs})
+            if best is None or gbs > best["GB_s"]:
+                best = rows[-1]
+        print(f"[probe] {r} reads + 1 write: best {best['GB_s']:.0f} GB/s at {best['blocks']} workgroups",
+              file=sys.stderr, flush=True)
+    expect = sum(1.0 + k for k in range(6))
+    ok = bool(torch.all(dst == expect).item())
+    out = {"metric": "streaming ceiling (HBM GB/s of dst = sum of r arrays)", "unit": "GB/s",
+           "peak": HBM_PEAK_GBS, "array_MiB": args.probe_mib, "result_checked": ok,
+           "best": {str(r): max((x for x in rows if x["reads"] == r), key=lambda x: x["GB_s"]) for r in (1, 2, 4, 6)},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
 
 
 def _calibrate_copy(args, torch, out):
@@ -385,7 +429,9 @@ def bench_diff3d(args, W, K, np, torch):
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": _traffic(os.path.join(ROOT, "profiles", "traffic_diff3d.json"),
                                          f"diff3d-{args.precision}-q{args.q}"),
-                     "kernel": "kiops_solve_kernel<Stencil3D>", "algorithmic_bytes_per_launch": alg,
+                     "kernel": (f"kiops_solve_kernel<{'Stencil3DNarrow' if args.q in (1, 2) else 'Stencil3D'}"
+                                f"<{'double' if args.precision == 'fp64' else 'float'}>> (one persistent launch per solve)"),
+                     "algorithmic_bytes_per_launch": alg,
                      "avg_launch_ms": sum(ms) / len(ms)},
         "latency_ms": _lat(ms),
         "solve": {k: st[k] for k in ("matvecs", "substeps", "rejections", "m_last", "grid_blocks")},
