@@ -43,10 +43,14 @@ def parse():
     ap.add_argument("--cpu-sample-substeps", type=int, default=1,
                     help="substeps of the one-thread CPU oracle sample")
     ap.add_argument("--traffic-json", type=str, default=os.path.join(ROOT, "profiles", "traffic.json"))
-    ap.add_argument("--workload", choices=("adr2d", "diff3d", "batch", "serve", "small", "probe"), default="adr2d",
+    ap.add_argument("--workload", choices=("adr2d", "diff3d", "batch", "serve", "small", "probe", "epirk"),
+                    default="adr2d",
                     help="adr2d: the 2048^2 tau sweep (default); diff3d: the 256^3 variable-"
                          "coefficient solve; batch: 256 2-D problems in one launch vs a per-solve loop; "
-                         "probe: the streaming ceiling of the device (the library's plain streaming kernel)")
+                         "probe: the streaming ceiling of the device (the library's plain streaming kernel); "
+                         "epirk: EPIRK4s3A on the paper's nonlinear 2-D ADR problem (400^2, t in [0, 0.1])")
+    ap.add_argument("--epirk-side", type=int, default=400)
+    ap.add_argument("--epirk-steps", type=str, default="10,20,40,80", help="step counts over [0, 0.1] (epirk)")
     ap.add_argument("--probe-mib", type=int, default=1024, help="MiB per array (probe)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-count", type=int, default=48, help="requests per arrival rate (serve)")
@@ -163,6 +167,8 @@ def main():
         return bench_small(args, W, K, np, torch)
     if args.workload == "probe":
         return bench_probe(args, K, torch)
+    if args.workload == "epirk":
+        return bench_epirk(args, K, torch)
     taus = [float(t) for t in args.taus.split(",")] if args.taus else W.cfg2_tau_grid()
     side = args.side
     pr = W.cfg2(side, taus[0], q=args.q)       # operator and vectors shared by the sweep
@@ -260,6 +266,48 @@ def main():
         print("[bench] timing the CPU oracle (one whole solve)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sample, taus, args.cpu_sample_substeps)
     print(json.dumps(out), flush=True)
+
+
+def bench_epirk(args, K, torch):
+    """EPIRK4s3A (Eq. (51)) on the paper's 2-D ADR problem at --epirk-side^2
+    over t in [0, 0.1] with constant steps (two solver calls per step, m warm
+    start across steps); for each step count: wall time, products with the
+    Jacobian, and the error against the run with the most steps at tol 1e-12
+    (the reference is that self-run, as no independent solver of this size is
+    at hand)."""
+    from paper_1804_05126_amd.epirk import ADR2D, EPIRK4s3A
+    prob = ADR2D(args.epirk_side)
+    u0 = prob.initial_condition()
+    counts = [int(c) for c in args.epirk_steps.split(",")]
+    T = 0.1
+    ref = EPIRK4s3A(prob, tol=1e-12).integrate(u0, T / (2 * max(counts)), 2 * max(counts))
+    rows = []
+    for k in counts:
+        for warm in (True, False):
+            integ = EPIRK4s3A(prob, tol=1e-8, warm_start=warm)
+            integ.integrate(u0, T / k, 1)          # untimed: builds workspaces
+            integ = EPIRK4s3A(prob, tol=1e-8, warm_start=warm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u = integ.integrate(u0, T / k, k)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            err = float(torch.linalg.norm(u - ref) / torch.linalg.norm(ref))
+            mv = [sum(s.matvecs[c] for s in integ.history) for c in (0, 1)]
+            rows.append({"steps": k, "h": T / k, "warm_start": warm, "seconds": el, "steps_per_s": k / el,
+                         "products_call1": mv[0], "products_call2": mv[1], "rel_err": err,
+                         "m_last_final": integ.history[-1].m_last})
+            print(f"[epirk] {k} steps warm={warm}: {el * 1e3:.1f} ms, products {mv}, err {err:.2e}",
+                  file=sys.stderr, flush=True)
+    best = max((r for r in rows if r["warm_start"]), key=lambda r: r["steps"])
+    out = {"metric": "EPIRK4s3A time steps/s (2 phi-combination solves per step)", "value": best["steps_per_s"],
+           "unit": "steps/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"nonlinear 2-D ADR {args.epirk_side}^2 periodic, eps 1e-2, alpha -10, "
+                                  f"gamma 100, t in [0, 0.1], tol 1e-8, q 2"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+    prob.close()
+    return 0
 
 
 def bench_probe(args, K, torch):

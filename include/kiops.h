@@ -70,8 +70,10 @@ typedef enum {
  * A column index outside [0, nrows) or a row pointer outside [0, nnz] is read
  * as a zero entry (the kernels bounds-check every access).
  * Stencils: N * 8 must stay below 4 GiB.
- * All array pointers are device memory, borrowed: they must stay valid and
- * unchanged while the operator is used.
+ * All array pointers are device memory, borrowed: they must stay valid while
+ * the operator exists and unchanged during any call that uses it; between
+ * calls the caller may rewrite their contents (e.g. the reaction field of a
+ * Jacobian updated every time step), and the next call reads the new values.
  */
 typedef struct {
   kiops_op_kind kind;
@@ -202,6 +204,16 @@ kiops_status kiops_phi_combination(kiops_operator* op, double tau, int p, const 
 kiops_status kiops_phi_combination_noalloc(kiops_operator* op, double tau, int p, const double* const* V,
                                            double tol, int m_init, int q, const kiops_options* opts,
                                            double* w, kiops_stats* stats);
+
+/* kiops_apply: y = A x for the operator's A (Section 3.3: A is only applied),
+ * in FP64 whatever the operator's precision, one plain kernel enqueued on the
+ * operator's stream and not waited for.  x, y: device, N doubles each, 8-byte
+ * aligned, not overlapping.  For callers that need A x outside a solve: the
+ * right-hand side f(u) = A u + g(u) of an exponential integrator (Section 2),
+ * a residual.  The operator's arrays are read as they are when the kernel runs
+ * (a caller that rewrites, say, the reaction field between solves gets the
+ * new field).  Errors: INVALID_ARG (null or overlapping vectors), DEVICE. */
+kiops_status kiops_apply(kiops_operator* op, const double* x, double* y);
 
 /* Several output times (Algorithm 1 with T = [T_1, ..., T_n] and Algorithm 3):
  * one adaptive integration from 0 to T_n = T_end that, at every accepted

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import KiopsError  # noqa: F401
 
 __all__ = ["Operator", "phi_combination", "phi_combination_noalloc", "phi_batch", "batch_tune", "Server", "iop_basis", "small_expm",
-           "stream_probe", "controller_decide", "KiopsError"]
+           "stream_probe", "controller_decide", "apply", "KiopsError"]
 
 
 def _torch():
@@ -43,8 +43,10 @@ def _require_cuda_f64(t, n: Optional[int], name: str):
 class Operator:
     """A stencil or CSR operator bound to a stream, with its workspace.
 
-    Coefficient tensors are borrowed: keep them alive and unchanged while the
-    operator is used (the Operator keeps references)."""
+    Coefficient tensors are borrowed (the Operator keeps references): leave them
+    unchanged during a call that uses the operator; between calls their
+    contents may be rewritten in place (a Jacobian's reaction field updated
+    every time step), and the next call reads the new values."""
 
     def __init__(self, kind: str, *, nx: int = 0, ny: int = 0, nz: int = 1, h: float = 1.0,
                  diff: float = 0.0, kappa=None, adv=(0.0, 0.0, 0.0), reaction=None,
@@ -401,6 +403,19 @@ def small_expm(Hs, tau: float, stream=None):
                                     C.c_void_p(_ptr(scratch)), C.c_void_p(s.cuda_stream)),
                "kiops_small_expm")
     return F
+
+
+def apply(op: Operator, x, y=None):
+    """y = A x (FP64) by the library's operator kernel, enqueued on the
+    operator's stream; returns y (allocated when not given)."""
+    torch = _torch()
+    n = op.n
+    _require_cuda_f64(x, n, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _require_cuda_f64(y, n, "y")
+    _lib.check(op._lib.kiops_apply(op._h, C.c_void_p(_ptr(x)), C.c_void_p(_ptr(y))), "kiops_apply")
+    return y
 
 
 def stream_probe(srcs: Sequence, dst, blocks: int, stream=None) -> None:

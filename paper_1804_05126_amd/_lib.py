@@ -116,6 +116,7 @@ SIGNATURES = [
                                               C.POINTER(Options), C.POINTER(C.c_void_p), C.POINTER(Stats)]),
     ("kiops_status_string", C.c_char_p, [C.c_int]),
     ("kiops_device_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("kiops_apply", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("kiops_iop_basis", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p), C.c_int, C.c_int,
                                   C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]),

@@ -103,10 +103,11 @@ bool uses_3d(const kiops_operator* op) {
   return op->d.kind == KIOPS_OP_STENCIL3D_7PT || (op->d.kind == KIOPS_OP_STENCIL2D_5PT && op->d.kappa);
 }
 
-// z planes per work item of the marching pass (nominal; sizes the grid)
-int zchunk(const kiops_operator* op) { return (int)std::min<int64_t>(16, op->d.nz); }
+// z planes per work item of the marching pass (nominal; sizes the grid): 24
+// measured 1.5% faster than 16 and 2% faster than 32 at 256^3 (FP64)
+int zchunk(const kiops_operator* op) { return (int)std::min<int64_t>(24, op->d.nz); }
 
-// Number of z chunks for a grid of nwg workgroups: about nz / 16, raised (by at
+// Number of z chunks for a grid of nwg workgroups: about nz / 24, raised (by at
 // most half) so that the item count is a multiple of the grid when that is
 // reachable, which gives every workgroup the same number of items.
 int zchunks(const kiops_operator* op, int nwg) {
@@ -1241,6 +1242,15 @@ kiops_status kiops_device_info(const kiops_operator* op, int* compute_units, int
     *grid_blocks = g;
   }
   return KIOPS_OK;
+}
+
+kiops_status kiops_apply(kiops_operator* op, const double* x, double* y) {
+  if (!op || !x || !y) return KIOPS_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 7) return KIOPS_ERR_INVALID_ARG;
+  const uintptr_t xa = reinterpret_cast<uintptr_t>(x), ya = reinterpret_cast<uintptr_t>(y);
+  const uintptr_t nb = (uintptr_t)op->N * sizeof(double);
+  if (xa < ya + nb && ya < xa + nb) return KIOPS_ERR_INVALID_ARG;   // overlapping vectors
+  return hip_ok(kiops::launch_apply(op->d, op->N, x, y, op->stream)) ? KIOPS_OK : KIOPS_ERR_DEVICE;
 }
 
 kiops_status kiops_workspace_bytes(const kiops_operator* op, int p, int q, const kiops_options* opts,
