@@ -6,6 +6,7 @@
         extend the IOP basis to m (Algorithm 2)
         F = exp(tau H~), H~ = [[H_j, e_1], [0, 0]]                        Eqs. (37)-(38)
         eps = beta |h_{j+1,j}| |F(j, j+1)|                                Eq. (36)
+              (or a variant of Section 3.4, below)
         decision (Algorithm 4)
         accepted: w = beta V(1:N, 1:j) F(1:j, 1); T_now += tau             Alg. 3, Eq. (33)
         rejected: extend the basis (j < m_max) or shrink tau (j = m_max)
@@ -15,6 +16,17 @@ the paper's method, not the exact result: it serves to compare the device
 controller's decisions (substeps, rejections, Krylov sizes) with the same
 algorithm run on the CPU.  The exact result comes from ``augmented``,
 ``spectral`` or ``arnoldi``.
+
+Error-estimate variants (Section 3.4; the error of Eq. (33) is the series
+Eq. (35), whose first term is Eq. (36)):
+  "one"        Eq. (36): beta |h| |a|,  a = tau e_j^T phi_1(tau H_j) e_1
+  "two"        the first two terms of Eq. (35): beta |h| ||a v_{j+1} + b A~ v_{j+1}||,
+               b = tau^2 e_j^T phi_2(tau H_j) e_1
+  "corrected"  the corrected scheme named after Eq. (30): the result takes the
+               first term, w += beta h a v_{j+1}(1:N), and eps is the second
+               term alone, beta |h| |b| ||A~ v_{j+1}||
+a and b are entries of exp(tau [[H_j, e_1, 0], [0, 0, 1], [0, 0, 0]]) (Theorem 1
+applied to H_j); A~ v_{j+1} is one more product with the augmented matrix.
 """
 
 from __future__ import annotations
@@ -45,7 +57,7 @@ class KiopsStats:
 def kiops(apply_A: Callable[[np.ndarray], np.ndarray], T_end: float,
           vectors: Sequence[np.ndarray], tol: float = 1e-7, m_init: int = 10,
           m_min: int = 10, m_max: int = 128, q: int = 2,
-          max_substeps: int = 100000, normalize_B: bool = True):
+          max_substeps: int = 100000, normalize_B: bool = True, estimate: str = "one"):
     vectors = [np.asarray(v, dtype=np.float64) for v in vectors]
     p = len(vectors) - 1
     st = KiopsStats()
@@ -70,12 +82,27 @@ def kiops(apply_A: Callable[[np.ndarray], np.ndarray], T_end: float,
             basis.extend(cs.m)
             st.matvecs += basis.j - before
             j = basis.j
-            Ht = np.zeros((j + 1, j + 1))
+            extra = 0 if estimate == "one" else 1
+            Ht = np.zeros((j + 1 + extra, j + 1 + extra))
             Ht[:j, :j] = basis.H[:j, :j]
             Ht[0, j] = 1.0
+            if extra:
+                Ht[j, j + 1] = 1.0
             F = expm(cs.tau * Ht)
             st.expms += 1
-            eps = 0.0 if basis.breakdown else basis.beta * abs(basis.H[j, j - 1]) * abs(F[j - 1, j])
+            h = basis.H[j, j - 1]
+            a = F[j - 1, j]
+            if basis.breakdown:
+                eps = 0.0
+            elif estimate == "one":
+                eps = basis.beta * abs(h) * abs(a)
+            else:
+                b = F[j - 1, j + 1]
+                Av = basis.apply_aug(basis.V[j])
+                if estimate == "two":
+                    eps = basis.beta * abs(h) * np.linalg.norm(a * basis.V[j] + b * Av)
+                else:
+                    eps = basis.beta * abs(h) * abs(b) * np.linalg.norm(Av)
             d = decide(cs, j, eps, basis.breakdown)
             record(cs, d, j, eps)
             st.last_omega = d.omega
@@ -84,6 +111,8 @@ def kiops(apply_A: Callable[[np.ndarray], np.ndarray], T_end: float,
                 if basis.breakdown:
                     st.breakdowns += 1
                 w = basis.beta * (basis.V[:j, :basis.N].T @ F[:j, 0])
+                if estimate == "corrected" and not basis.breakdown:
+                    w = w + basis.beta * h * a * basis.V[j, :basis.N]
                 cs.T_now = cs.T_now + cs.tau
                 if T_end - cs.T_now <= 8.0 * np.finfo(float).eps * T_end:
                     cs.T_now = T_end
