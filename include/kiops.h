@@ -99,8 +99,27 @@ typedef struct {
   int32_t m_min;
   int32_t m_max;
   int32_t max_substeps;
-  int32_t reserved;
+  int32_t estimate;   /* KIOPS_ESTIMATE_*: the error estimate of an attempt (Section 3.4) */
 } kiops_options;
+
+/* kiops_options.estimate.  Every variant takes its terms from the expansion
+ * of the error, Eq. (35), whose first term is Eq. (36):
+ *   ONE_TERM  (0, default): eps = beta |h_{m+1,m}| |tau e_m^T phi_1(tau H_m) e_1|, Eq. (36);
+ *   TWO_TERM  (1): the norm of the first two terms of Eq. (35),
+ *       eps = beta |h_{m+1,m}| || a v_{m+1} + b A~ v_{m+1} ||,
+ *       a = tau e_m^T phi_1(tau H_m) e_1,  b = tau^2 e_m^T phi_2(tau H_m) e_1,
+ *     where <v_{m+1}, A~ v_{m+1}> and ||A~ v_{m+1}|| come from the pass that
+ *     formed v_{m+1} (it computes A~ v_{m+1} anyway), so it costs no product;
+ *   CORRECTED (2): the corrected scheme (remark after Eq. (30)): the result
+ *       also takes the first term of Eq. (35), beta h_{m+1,m} a v_{m+1}, and
+ *       eps is the norm of the second term, beta |h_{m+1,m}| |b| ||A~ v_{m+1}||.
+ * a and b come from one exponential of the (m+2) x (m+2) matrix
+ * [[H_m, e_1, 0], [0, 0, 1], [0, 0, 0]] (Theorem 1 applied to H_m).  The
+ * batched and served forms take ONE_TERM only; CORRECTED is not combined with
+ * several output times (UNSUPPORTED and INVALID_ARG respectively). */
+#define KIOPS_ESTIMATE_ONE_TERM 0
+#define KIOPS_ESTIMATE_TWO_TERM 1
+#define KIOPS_ESTIMATE_CORRECTED 2
 
 #define KIOPS_M_MAX_LIMIT 128
 #define KIOPS_P_MAX 8

@@ -154,15 +154,17 @@ def _vec_ptrs(vectors: Sequence, n: int):
 
 def phi_combination(op: Operator, tau: float, vectors: Sequence, tol: float = 1e-8,
                     m_init: int = 10, q: int = 2, m_min: int = 0, m_max: int = 0,
-                    max_substeps: int = 0, out=None, check: bool = True):
-    """w = sum_k tau^k phi_k(tau A) vectors[k]; returns (w, stats dict, status)."""
+                    max_substeps: int = 0, out=None, check: bool = True, estimate: int = 0):
+    """w = sum_k tau^k phi_k(tau A) vectors[k]; returns (w, stats dict, status).
+    estimate: 0 the one-term error estimate (Eq. (36)), 1 the first two terms
+    of Eq. (35), 2 the corrected scheme (KIOPS_ESTIMATE_*)."""
     torch = _torch()
     p = len(vectors) - 1
     V = _vec_ptrs(vectors, op.n)
     w = out if out is not None else torch.empty(op.n, dtype=torch.float64, device="cuda")
     _require_cuda_f64(w, op.n, "w")
     op.ensure_workspace(op.workspace_bytes(p, q, m_min, m_max, max_substeps))
-    o = _lib.Options(m_min, m_max, max_substeps, 0)
+    o = _lib.Options(m_min, m_max, max_substeps, int(estimate))
     st = _lib.Stats()
     status = op._lib.kiops_phi_combination(op._h, float(tau), p, V, float(tol), int(m_init), int(q),
                                            C.byref(o), C.c_void_p(_ptr(w)), C.byref(st))
@@ -191,7 +193,7 @@ def phi_combination_noalloc(op: Operator, tau: float, vectors: Sequence, out, to
 
 def phi_combination_times(op: Operator, times: Sequence[float], vectors: Sequence, task: int = 2,
                           tol: float = 1e-8, m_init: int = 10, q: int = 2, m_min: int = 0, m_max: int = 0,
-                          max_substeps: int = 0, outs=None, check: bool = True):
+                          max_substeps: int = 0, outs=None, check: bool = True, estimate: int = 0):
     """Several output times T_1 < ... < T_n in one integration (Algorithms 1 and 3):
     outs[k] = sum_i T_k^i phi_i(T_k A) vectors[i] (task 2), times (1/T_k)^p for
     task 1.  Returns (list of w, stats dict, status)."""
@@ -206,7 +208,7 @@ def phi_combination_times(op: Operator, times: Sequence[float], vectors: Sequenc
     for o in outs:
         _require_cuda_f64(o, op.n, "outs")
     op.ensure_workspace(op.workspace_bytes(p, q, m_min, m_max, max_substeps))
-    o = _lib.Options(m_min, m_max, max_substeps, 0)
+    o = _lib.Options(m_min, m_max, max_substeps, int(estimate))
     st = _lib.Stats()
     T = (C.c_double * n)(*[float(t) for t in times])
     Wp = (C.c_void_p * n)(*[_ptr(x) for x in outs])

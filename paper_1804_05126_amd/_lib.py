@@ -52,7 +52,7 @@ class OperatorDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("m_min", C.c_int32), ("m_max", C.c_int32), ("max_substeps", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("estimate", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -216,6 +216,12 @@ kiops_status grid_size(const kiops_operator* op, int p, int q, int* nwg) {
 // 64 / 32: 2.6e-4 / 6.7e-6 / 1.6e-6 on the 256^3 constant-coefficient box,
 // 1.8e-4 / 1.8e-4 / 9.9e-7 and 3.2e-5 / 3.2e-5 / 5.6e-6 on small 3-D boxes
 // with tau ||A||_1 of 306 and 101).
+// The error estimate an options block asks for (KIOPS_ESTIMATE_*), or -1 if invalid.
+int resolve_estimate(const kiops_options* o) {
+  const int e = o ? o->estimate : KIOPS_ESTIMATE_ONE_TERM;
+  return (e >= KIOPS_ESTIMATE_ONE_TERM && e <= KIOPS_ESTIMATE_CORRECTED) ? e : -1;
+}
+
 void resolve_options(const kiops_operator* op, const kiops_options* o, int* m_min, int* m_max,
                      int* max_sub) {
   const int m_default = op->d.precision == KIOPS_MIXED ? 32 : 128;
@@ -673,6 +679,7 @@ kiops_status plan_batch(int count, const kiops_problem* probs, const kiops_optio
   }
   resolve_options(probs[0].op, opts, &B.m_min, &B.m_max, &B.max_sub);
   if (B.m_max > KIOPS_M_MAX_LIMIT || B.m_min > B.m_max || B.m_min < 1) return KIOPS_ERR_INVALID_ARG;
+  if (resolve_estimate(opts) != KIOPS_ESTIMATE_ONE_TERM) return KIOPS_ERR_UNSUPPORTED;
   B.pb = p_bucket(pmax);
   B.fn = group_kernel_for(probs[0].op, B.pb);
   if (!B.fn) return KIOPS_ERR_UNSUPPORTED;
@@ -1131,6 +1138,8 @@ kiops_status phi_combination_in(kiops_operator* op, char* ws, size_t ws_bytes, d
   int m_min, m_max, max_sub;
   resolve_options(op, opts, &m_min, &m_max, &max_sub);
   if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max || m_min < 1) return KIOPS_ERR_INVALID_ARG;
+  const int estimate = resolve_estimate(opts);
+  if (estimate < 0) return KIOPS_ERR_INVALID_ARG;
   if (q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
   if (!kernel_for(op, p, q)) return KIOPS_ERR_UNSUPPORTED;
   if (stats) std::memset(stats, 0, sizeof(*stats));
@@ -1151,6 +1160,7 @@ kiops_status phi_combination_in(kiops_operator* op, char* ws, size_t ws_bytes, d
   }
   if (!ws || ws_bytes < L.total) return KIOPS_ERR_OUT_OF_MEMORY;
   KParams P = make_params(op, L, ws, tau, p, V, tol, m_init, q, m_min, m_max, max_sub, kModeSolve, w);
+  P.estimate = estimate;
   Ctrl hc{};
   unsigned abort_flag = 0;
   s = run_solve(op, ws, L, P, p, V, &hc, &abort_flag);
@@ -1310,6 +1320,8 @@ kiops_status kiops_phi_combination_times(kiops_operator* op, int n, const double
   int m_min, m_max, max_sub;
   resolve_options(op, opts, &m_min, &m_max, &max_sub);
   if (m_max > KIOPS_M_MAX_LIMIT || m_min > m_max || m_min < 1) return KIOPS_ERR_INVALID_ARG;
+  const int estimate = resolve_estimate(opts);
+  if (estimate < 0 || (estimate == KIOPS_ESTIMATE_CORRECTED && n > 1)) return KIOPS_ERR_INVALID_ARG;
   if (q > kWinMax) return KIOPS_ERR_UNSUPPORTED;
   if (!kernel_for(op, p, q)) return KIOPS_ERR_UNSUPPORTED;
   if (stats) std::memset(stats, 0, sizeof(*stats));
@@ -1323,6 +1335,7 @@ kiops_status kiops_phi_combination_times(kiops_operator* op, int n, const double
                           max_sub, kModeSolve, w);
   P.ntimes = n;
   P.task1 = task == 1 ? 1 : 0;
+  P.estimate = estimate;
   for (int k = 0; k < n; ++k) {
     P.times[k] = times[k];
     P.wout[k] = W[k];

@@ -55,7 +55,7 @@ struct Ctrl {
   int32_t jg;        // gather: number of basis vectors
   int32_t status;
   int32_t mode;
-  int32_t pad0;
+  int32_t estimate;  // KIOPS_ESTIMATE_*
   double a;                    // R_kp = a U_{kp-1} + sum_i bw[i] R_i
   double bw[kLdh];
   double yb_prev[kPM];         // nu * y(R_{kp-1}): B term of U_{kp-1}
@@ -93,6 +93,9 @@ struct Ctrl {
   uint64_t t_release_max, t_release_mean;   // delay until a workgroup sees the release
   uint64_t t_red, t_pub, t_ser;   // epilogues of passes: partial-sum reduction, control-block copy,
                                   // serial normalisation and coefficients
+  // the latest normalised vector v_k: <v_k, A~ v_k> and ||A~ v_k||^2 (the
+  // two-term and corrected error estimates use them for v_{m+1})
+  double est_c, est_u;
 };
 
 // Release word and abort flag on separate 128-byte lines: every workgroup
@@ -116,6 +119,7 @@ struct KParams {
   int poll_sleep;              // barrier polls: s_sleep(2) repeats between two reads of a flag
   int ranks;                   // workgroups per CU of a grid that fills every CU evenly, else 1
   int expm_grid;               // padded size from which the small exponential runs on the whole grid (0: never)
+  int estimate;                // error estimate of an attempt: KIOPS_ESTIMATE_* (Section 3.4)
   double T_end, tol;
   double elem_bytes;           // bytes per basis element (8 or 4)
   double coef_streams;         // per-cell coefficient arrays the operator reads

@@ -402,8 +402,23 @@ __device__ void begin_outputs(const KParams& P, SmallState& S, int j, double* ld
   }
 }
 
+// Error estimate of an attempt with basis size j (Section 3.4) from F =
+// exp(tau H~): the first term of Eq. (35), which is Eq. (36), or (with the
+// extra row and column of the two-term exponential, F(j, j+2) =
+// tau^2 e_j^T phi_2(tau H_j) e_1) the first two terms or the second alone.
+// v_{j+1} is the latest normalised vector: est_c = <v, A~ v>, est_u = ||A~ v||^2.
+__device__ inline double attempt_estimate(const Ctrl& C, double h, const double* F, int j) {
+  const double a = F[(j - 1) * kExpmLd + j];
+  if (C.estimate == KIOPS_ESTIMATE_ONE_TERM) return C.beta * fabs(h) * fabs(a);
+  const double b = F[(j - 1) * kExpmLd + j + 1];
+  const double u = C.est_u > 0.0 ? C.est_u : 0.0;
+  if (C.estimate == KIOPS_ESTIMATE_CORRECTED) return C.beta * fabs(h) * fabs(b) * sqrt(u);
+  const double q2 = a * a + 2.0 * a * b * C.est_c + b * b * u;   // ||a v + b A~ v||^2
+  return C.beta * fabs(h) * sqrt(q2 > 0.0 ? q2 : 0.0);
+}
+
 // Decision for an attempt with basis size j whose exponential F = exp(tau H~)
-// is in slot `slot` of the scratch: eps (Eq. (36)), Algorithm 4, and on
+// is in slot `slot` of the scratch: eps (Section 3.4), Algorithm 4, and on
 // acceptance the gather coefficients.  Whole workgroup.  Returns true when
 // the attempt is to be repeated on the same basis with a smaller tau
 // (rejection at m_max).
@@ -412,7 +427,7 @@ __device__ bool attempt_decide(const KParams& P, SmallState& S, int j, bool brea
   const double* F = P.expm + (size_t)slot * kExpmSlot;
   if (threadIdx.x == 0) {
     const double tau = C.tau;
-    const double eps = breakdown ? 0.0 : C.beta * fabs(h_get(S, j + 1, j)) * fabs(F[(j - 1) * kExpmLd + j]);
+    const double eps = breakdown ? 0.0 : attempt_estimate(C, h_get(S, j + 1, j), F, j);
     CtrlIn ci;
     ci.T_end = C.T_end; ci.tol = C.tol; ci.T_now = C.T_now; ci.tau = tau;
     ci.m_min = C.m_min; ci.m_max = C.m_max; ci.m = C.m; ci.have_old = C.have_old;
@@ -462,8 +477,13 @@ __device__ bool attempt_decide(const KParams& P, SmallState& S, int j, bool brea
   if (C.phase == kPhaseGather) {
     // gather coefficients c_i = beta F(i, 1) / s_{i-1}
     for (int i = 1 + threadIdx.x; i <= j; i += kThreads) C.cg[i] = C.beta * F[(i - 1) * kExpmLd] * S.sinv[i];
+    if (threadIdx.x == 0 && C.estimate == KIOPS_ESTIMATE_CORRECTED && !breakdown) {
+      // corrected scheme: + beta h_{j+1,j} (tau e_j^T phi_1(tau H_j) e_1) v_{j+1}
+      C.cg[j + 1] = C.beta * h_get(S, j + 1, j) * F[(j - 1) * kExpmLd + j] * S.sinv[j + 1];
+      C.jg = j + 1;
+    }
     __syncthreads();
-    begin_outputs(P, S, j, lds);
+    begin_outputs(P, S, C.jg, lds);
   }
   return S.again != 0;
 }
@@ -473,11 +493,13 @@ __device__ bool attempt_decide(const KParams& P, SmallState& S, int j, bool brea
 // (phase kPhaseExpm, continued by epilogue_expm).  Whole workgroup.
 __device__ void attempt_run(const KParams& P, SmallState& S, int j, bool breakdown, double* lds) {
   Ctrl& C = S.C;
-  const int n = j + 1;
+  const int extra = C.estimate != KIOPS_ESTIMATE_ONE_TERM ? 1 : 0;   // the phi_2 column of the two-term estimate
+  const int n = j + 1 + extra;
   const int n16 = pad16(n);
   for (;;) {
     const double tau = C.tau;
-    // X = tau H~ (Eq. (37)) by columns, with its 1-norm
+    // X = tau H~ (Eq. (37)) by columns, with its 1-norm; with the extra row
+    // and column, tau [[H, e_1, 0], [0, 0, 1], [0, 0, 0]] (Theorem 1 on H)
     double* A = P.expm;
     const bool full = C.q == 0;   // full window: H in device memory, else the band in LDS
     double colmax = 0.0;
@@ -487,6 +509,7 @@ __device__ void attempt_run(const KParams& P, SmallState& S, int j, bool breakdo
         double v = 0.0;
         if (r < j && c < j) v = tau * (full ? P.H[(r + 1) * kLdh + (c + 1)] : h_get(S, r + 1, c + 1));
         else if (c == j && r == 0) v = tau;
+        else if (extra && r == j && c == j + 1) v = tau;
         A[r * kExpmLd + c] = v;
         cs += fabs(v);
       }
@@ -556,7 +579,7 @@ __device__ __forceinline__ int expm_participants(int n16, int nwg) {
 template <class F>
 __device__ inline void expm_phase(const KParams& P, SmallState& S, unsigned& epoch, double* lds, F&& epi) {
   const Ctrl& C = *P.ctrl;
-  const int n = uniform(C.e_j) + 1;
+  const int n = uniform(C.e_j) + 1 + (uniform(C.estimate) != KIOPS_ESTIMATE_ONE_TERM ? 1 : 0);
   const int d = uniform(C.e_d), s = uniform(C.e_s), nst = uniform(C.e_nst);
   const double alpha = uniform(C.e_alpha);
   const int npart = expm_participants(pad16(n), P.nwg);
@@ -603,6 +626,7 @@ __device__ __noinline__ void epilogue_setup(const KParams& P, SmallState& S, dou
     C.m_new = C.m;
     C.status = KIOPS_OK;
     C.mode = P.mode;
+    C.estimate = P.estimate;
     C.alg_bytes = (double)P.p * 8.0 * (double)P.N;   // ||B||_1
     if (!isfinite(nb)) {
       C.status = KIOPS_ERR_NONFINITE;
@@ -664,6 +688,8 @@ __device__ inline int step_normalise(const KParams& P, SmallState& S, int k, dou
   S.sinv[k] = si;
   P.sinv[k] = si;
   S.unorm_prev = sqrt(UU) * si;
+  C.est_c = Ck * si * si;                     // <v_k, A~ v_k>
+  C.est_u = UU * si * si;                     // ||A~ v_k||^2
   Ck_out = Ck;
   si_out = si;
   return -1;
