@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--side", type=int, default=2048)
     ap.add_argument("--taus", type=str, default="")
     ap.add_argument("--q", type=int, default=2)
+    ap.add_argument("--estimate", type=int, default=0, choices=(0, 1, 2),
+                    help="error estimate (Section 3.4): 0 Eq. (36), 1 two terms of Eq. (35), 2 corrected scheme")
     ap.add_argument("--precision", type=str, default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-substeps", type=int, default=1,
@@ -184,7 +186,7 @@ def main():
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
-        _, st, _ = K.phi_combination(op, tau, vecs, tol=tol, m_init=10, q=args.q, out=w)
+        _, st, _ = K.phi_combination(op, tau, vecs, tol=tol, m_init=10, q=args.q, out=w, estimate=args.estimate)
         ev1.record(stream)
         return ev0, ev1, st
 
@@ -236,7 +238,7 @@ def main():
                          f"r~U[-1,0], p=3, b_k~N(0,1), tau sweep {taus}, tol {tol:g}, IOP q={args.q}, "
                          f"m_init=10, m_max={records[0][3]['m_max']}"),
             "solves_per_step": len(taus),
-            "precision": args.precision,
+            "precision": args.precision, "estimate": args.estimate,
             "seed": pr.seed,
         },
         "roofline": {
@@ -449,7 +451,8 @@ def bench_diff3d(args, W, K, np, torch):
     def one():
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        _, st, _ = K.phi_combination(op, pr.tau, vecs, tol=pr.tol, m_init=pr.m_init, q=args.q, out=w)
+        _, st, _ = K.phi_combination(op, pr.tau, vecs, tol=pr.tol, m_init=pr.m_init, q=args.q, out=w,
+                                     estimate=args.estimate)
         e1.record(stream)
         return e0, e1, st
     for _ in range(args.warmup):
@@ -472,7 +475,7 @@ def bench_diff3d(args, W, K, np, torch):
         "dtype": "f64" if args.precision == "fp64" else "f32-basis/f64-accumulate", "data": "synthetic",
         "config": {"workload": (f"3D 7-point diffusion-reaction 256^3 periodic (N={pr.n}), kappa = box-averaged "
                                 f"exp(N(0,0.5^2)), r~U[-5,0], p=2, tau=1e-3, tol {pr.tol:g}, IOP q={args.q}"),
-                   "precision": args.precision, "seed": pr.seed},
+                   "precision": args.precision, "estimate": args.estimate, "seed": pr.seed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": _traffic(os.path.join(ROOT, "profiles", "traffic_diff3d.json"),
