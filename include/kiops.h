@@ -192,9 +192,9 @@ kiops_status kiops_set_workspace(kiops_operator* op, void* dev_ptr, size_t bytes
  *   m_init initial Krylov dimension, clamped into [m_min, m_max] (Algorithm 1).
  *   q     IOP window (Algorithm 2): each new basis vector is orthogonalised
  *         against the last q ones, 1..4 (the paper uses 2); 0 = against all
- *         of them (full Arnoldi), computed as classical Gram-Schmidt with one
- *         reorthogonalisation from the inner products of an extra phase per
- *         step.  5..8 return KIOPS_ERR_UNSUPPORTED.
+ *         of them (full Arnoldi), computed as classical Gram-Schmidt with a
+ *         Gram-matrix correction, h = c + (c - G c), from the inner products
+ *         of an extra phase per step.  5..8 return KIOPS_ERR_UNSUPPORTED.
  *   w     device, N entries, written with the result; may equal V[0], must not
  *         overlap any other V[k].
  *   stats may be NULL.

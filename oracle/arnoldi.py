@@ -28,6 +28,31 @@ from .augmented import trailing_entries
 from .expm import expm
 
 
+def arnoldi_basis(apply_aug: Callable[[np.ndarray], np.ndarray], v1: np.ndarray, m: int):
+    """m steps of the Arnoldi process from the unit vector v1, each new vector
+    orthogonalised against all earlier ones by classical Gram-Schmidt applied
+    twice.  Returns (V (m+1, n), H (m+1, m), k, happy): k steps were made; happy
+    when the process broke down (the new vector vanished)."""
+    n = v1.size
+    V = np.zeros((m + 1, n))
+    H = np.zeros((m + 1, m))
+    V[0] = v1
+    for j in range(m):
+        z = apply_aug(V[j])
+        pre = float(np.linalg.norm(z))
+        h = V[: j + 1] @ z
+        z = z - V[: j + 1].T @ h
+        h2 = V[: j + 1] @ z           # second pass of classical Gram-Schmidt
+        z = z - V[: j + 1].T @ h2
+        H[: j + 1, j] = h + h2
+        s = float(np.linalg.norm(z))
+        if s <= 1e-13 * pre:
+            return V, H, j + 1, True
+        H[j + 1, j] = s
+        V[j + 1] = z / s
+    return V, H, m, False
+
+
 def phi_combination_arnoldi(apply_A: Callable[[np.ndarray], np.ndarray], T: float,
                             vectors: Sequence[np.ndarray], tol_o: float = 1e-12,
                             m: int = 48, max_substeps: int = 100000, stats: dict = None,
@@ -67,27 +92,8 @@ def phi_combination_arnoldi(apply_A: Callable[[np.ndarray], np.ndarray], T: floa
         beta = float(np.linalg.norm(v0))
         if beta == 0.0:
             return np.zeros(N)
-        V = np.zeros((m + 1, N + p))
-        H = np.zeros((m + 1, m))
-        V[0] = v0 / beta
-        k = m
-        happy = False
-        for j in range(m):
-            z = apply_aug(V[j])
-            matvecs += 1
-            pre = float(np.linalg.norm(z))
-            h = V[: j + 1] @ z
-            z = z - V[: j + 1].T @ h
-            h2 = V[: j + 1] @ z           # second pass of classical Gram-Schmidt
-            z = z - V[: j + 1].T @ h2
-            H[: j + 1, j] = h + h2
-            s = float(np.linalg.norm(z))
-            if s <= 1e-13 * pre:
-                k = j + 1
-                happy = True
-                break
-            H[j + 1, j] = s
-            V[j + 1] = z / s
+        V, H, k, happy = arnoldi_basis(apply_aug, v0 / beta, m)
+        matvecs += k
         Ht = np.zeros((k + 1, k + 1))
         Ht[:k, :k] = H[:k, :k]
         Ht[0, k] = 1.0

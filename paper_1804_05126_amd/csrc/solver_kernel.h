@@ -797,9 +797,11 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
 
 // Epilogue after the inner-product phase of a full-window step (q = 0): the
 // orthogonalisation of A~ v_k against every earlier v_i by classical
-// Gram-Schmidt with one reorthogonalisation, reproduced from the inner
-// products: with c_i = <v_i, A~ v_k> and the Gram matrix G of v_1..v_k, the
-// two passes give h = c + (c - G c).  G and c live in device memory (P.G,
+// Gram-Schmidt with a Gram-matrix correction, from one set of inner products:
+// with c_i = <v_i, A~ v_k> and the Gram matrix G of v_1..v_k,
+// h = c + (c - G c) (what a second Gram-Schmidt pass would add if the
+// basis's own loss of orthogonality, I - G, were the only error; it is not a
+// second pass over fresh inner products).  G and c live in device memory (P.G,
 // P.fullc); the sums over i run on all threads.
 __device__ __noinline__ void epilogue_dots(const KParams& P, SmallState& S, double* lds) {
   Ctrl& C = S.C;
