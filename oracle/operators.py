@@ -11,6 +11,11 @@ differences, made periodic) and a 3-D variable-coefficient analogue:
 kf = the constant ``diff``, or the mean of the two cells' kappa.  Arrays are
 flattened with x fastest (index = x + nx (y + ny z)).
 
+General form (per-cell weights, the operator given by its stencil rows):
+    (A u)_i = W_0[i] u_i + W_1[i] u_{i+e_x} + W_2[i] u_{i-e_x} + W_3[i] u_{i+e_y}
+              + W_4[i] u_{i-e_y} [+ W_5[i] u_{i+e_z} + W_6[i] u_{i-e_z}]  (periodic)
+with 5 weights per cell in 2-D (nz = 1) and 7 in 3-D.
+
 ``stencil_apply`` uses whole-array shifts; ``stencil_sparse`` builds the same
 matrix entry by entry.  The two are written separately so each checks the other.
 """
@@ -26,9 +31,23 @@ def _axes(desc):
     return ((2, desc.nx, desc.adv[0]), (1, desc.ny, desc.adv[1]), (0, desc.nz, desc.adv[2]))
 
 
+def _weights(desc):
+    w = getattr(desc, "weights", None)
+    if w is None:
+        return None
+    return np.asarray(w, dtype=np.float64).reshape(-1, desc.nx * desc.ny * desc.nz)
+
+
 def stencil_apply(desc, u: np.ndarray) -> np.ndarray:
     shape = (desc.nz, desc.ny, desc.nx)
     U = np.asarray(u, dtype=np.float64).reshape(shape)
+    Wt = _weights(desc)
+    if Wt is not None:
+        out = Wt[0].reshape(shape) * U
+        for s, (axis, _, _) in enumerate(_axes(desc)[: (Wt.shape[0] - 1) // 2]):
+            out = out + Wt[1 + 2 * s].reshape(shape) * np.roll(U, -1, axis=axis)   # u_{i+e_d}
+            out = out + Wt[2 + 2 * s].reshape(shape) * np.roll(U, 1, axis=axis)    # u_{i-e_d}
+        return out.reshape(-1)
     if desc.reaction is not None:
         out = np.asarray(desc.reaction, dtype=np.float64).reshape(shape) * U
     else:
@@ -60,6 +79,22 @@ def stencil_sparse(desc) -> sp.csr_matrix:
     y = (idx // nx) % ny
     z = idx // (nx * ny)
     rows, cols, vals = [], [], []
+    Wt = _weights(desc)
+    if Wt is not None:
+        rows.append(idx)
+        cols.append(idx)
+        vals.append(Wt[0])
+        for d, size in enumerate((nx, ny, nz)[: (Wt.shape[0] - 1) // 2]):
+            coords = [x, y, z]
+            plus = [c.copy() for c in coords]
+            minus = [c.copy() for c in coords]
+            plus[d] = (coords[d] + 1) % size
+            minus[d] = (coords[d] - 1) % size
+            rows += [idx, idx]
+            cols += [plus[0] + nx * (plus[1] + ny * plus[2]), minus[0] + nx * (minus[1] + ny * minus[2])]
+            vals += [Wt[1 + 2 * d], Wt[2 + 2 * d]]
+        A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+        return A.tocsr()
     diag = np.zeros(n) if desc.reaction is None else np.asarray(desc.reaction, dtype=np.float64).copy()
     kap = None if desc.kappa is None else np.asarray(desc.kappa, dtype=np.float64)
     h = desc.h

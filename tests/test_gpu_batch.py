@@ -138,3 +138,28 @@ def test_batch_dominant_problem_gets_own_group():
         assert rel(w.cpu().numpy(), single.cpu().numpy()) <= 2e-8
     ref = augmented.phi_combination_dense(operators.dense(small.op), small.tau, small.vectors)
     assert rel(ws[1].cpu().numpy(), ref) <= 1e-8
+
+
+def test_batch_reports_start_and_end_clocks():
+    # each problem's device clocks: start before end, all inside the host's
+    # wall time of the call; a single solve reports them too
+    import time
+    import torch
+    import paper_1804_05126_amd as K
+    prs = _small_batch(16, seed=4011)
+    probs = _problems(prs)
+    announce("batch of 16: per-problem start and end clocks")
+    K.phi_batch(probs, group_size=8)             # warm: workspaces and code
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ws, stats, status, plan = K.phi_batch(probs, group_size=8)
+    wall = time.perf_counter() - t0
+    assert status == 0
+    starts = [st["clock_start_s"] for st in stats]
+    ends = [st["clock_end_s"] for st in stats]
+    assert all(e > s > 0.0 for s, e in zip(starts, ends))
+    span = max(ends) - min(starts)
+    announce(f"  device span {span * 1e3:.3f} ms, host wall {wall * 1e3:.3f} ms")
+    assert 0.0 < span <= wall
+    _, st, _ = K.phi_combination(probs[0]["op"], prs[0].tau, probs[0]["vectors"], tol=prs[0].tol)
+    assert st["clock_end_s"] > st["clock_start_s"] > 0.0

@@ -43,6 +43,9 @@ class StencilDesc:
     kappa: Optional[np.ndarray] = None      # per-cell diffusivity, float64[N]
     adv: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     reaction: Optional[np.ndarray] = None   # per-cell reaction r, float64[N]
+    # general form: per-cell weights [5|7][N] of the points (centre, +x, -x,
+    # +y, -y[, +z, -z]); the coefficient fields above are then unused
+    weights: Optional[np.ndarray] = None
 
     @property
     def kind(self) -> str:
