@@ -88,6 +88,11 @@ typedef struct {
   const int32_t* col;       /* device */
   const double* val;        /* device */
   kiops_precision precision;
+  /* General stencil form: per-cell weights [5|7][N] (device, borrowed), the
+   * points in the order centre, +x, -x, +y, -y (2-D), then +z, -z (3-D):
+   *   (A u)_i = W_0[i] u_i + W_1[i] u_{i+e_x} + W_2[i] u_{i-e_x} + ...  (periodic).
+   * With weights, kappa and reaction must be NULL and diff and adv zero. */
+  const double* weights;
 } kiops_operator_desc;
 
 /* Bounds of the Krylov dimension (Algorithm 1 inputs m_min, m_max; defaults
@@ -158,6 +163,10 @@ typedef struct {
   double time_serial_s;    /* normalisation, H column and next coefficients (thread 0) */
   int32_t pass_kind;       /* the pass that ran: KIOPS_PASS_* */
   int32_t reserved3;
+  /* device clock (constant rate, the same on every CU) at the start and at
+   * the end of the solve, in seconds from an arbitrary origin: in a batch,
+   * end - the batch's earliest start is the problem's completion time */
+  double clock_start_s, clock_end_s;
 } kiops_stats;
 
 /* kiops_stats.pass_kind */
@@ -166,6 +175,7 @@ typedef struct {
 #define KIOPS_PASS_MARCH2D 2   /* 5-point row-marching pass (large 2-D grids, windows of 1 and 2) */
 #define KIOPS_PASS_7PT 3       /* 7-point marching pass (3-D, and 2-D with a diffusivity field) */
 #define KIOPS_PASS_CSR 4       /* general sparse matrix */
+#define KIOPS_PASS_WEIGHTS 5   /* stencil given by per-cell weights (two phases per step) */
 
 typedef struct kiops_operator kiops_operator;
 

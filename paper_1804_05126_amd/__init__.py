@@ -49,7 +49,7 @@ class Operator:
     every time step), and the next call reads the new values."""
 
     def __init__(self, kind: str, *, nx: int = 0, ny: int = 0, nz: int = 1, h: float = 1.0,
-                 diff: float = 0.0, kappa=None, adv=(0.0, 0.0, 0.0), reaction=None,
+                 diff: float = 0.0, kappa=None, adv=(0.0, 0.0, 0.0), reaction=None, weights=None,
                  rowptr=None, col=None, val=None, precision: str = "fp64", stream=None):
         torch = _torch()
         lib = _lib.load()
@@ -83,6 +83,11 @@ class Operator:
                 _require_cuda_f64(reaction, self.n, "reaction")
                 d.reaction = _ptr(reaction)
                 self._keep.append(reaction)
+            if weights is not None:   # general form: [5|7][N] per-cell weights
+                nw = 5 if kind == "stencil2d" else 7
+                _require_cuda_f64(weights, nw * self.n, "weights")
+                d.weights = _ptr(weights)
+                self._keep.append(weights)
         self.kind = kind
         self.precision = precision
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -105,8 +110,10 @@ class Operator:
                        val=torch.as_tensor(desc.val, dtype=torch.float64, device=device),
                        precision=prec, stream=stream)
         f = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float64, device=device)  # noqa: E731
+        wts = getattr(desc, "weights", None)
         return cls(desc.kind, nx=desc.nx, ny=desc.ny, nz=desc.nz, h=desc.h, diff=desc.diff,
                    kappa=f(desc.kappa), adv=desc.adv, reaction=f(desc.reaction),
+                   weights=None if wts is None else f(wts).reshape(-1).contiguous(),
                    precision=prec, stream=stream)
 
     def close(self):

@@ -32,7 +32,7 @@ MIXED = 1
 M_MAX_LIMIT = 128
 P_MAX = 8
 EXPM_SCRATCH_DOUBLES = 9 * 144 * 144
-PASS_NAMES = {0: "Stencil2D", 1: "Stencil2DWide", 2: "Stencil2DMarch", 3: "Stencil3D", 4: "CsrOp"}
+PASS_NAMES = {0: "Stencil2D", 1: "Stencil2DWide", 2: "Stencil2DMarch", 3: "Stencil3D", 4: "CsrOp", 5: "WeightsOp"}
 
 
 class OperatorDesc(C.Structure):
@@ -47,6 +47,7 @@ class OperatorDesc(C.Structure):
         ("nrows", C.c_int64), ("nnz", C.c_int64),
         ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
         ("precision", C.c_int),
+        ("weights", C.c_void_p),
     ]
 
 
@@ -69,6 +70,7 @@ class Stats(C.Structure):
         ("status", C.c_int32), ("m_max", C.c_int32),
         ("time_reduce_s", C.c_double), ("time_publish_s", C.c_double), ("time_serial_s", C.c_double),
         ("pass_kind", C.c_int32), ("reserved3", C.c_int32),
+        ("clock_start_s", C.c_double), ("clock_end_s", C.c_double),
     ]
 
     def as_dict(self) -> dict:

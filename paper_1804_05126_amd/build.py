@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libkiops.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
            ("kiops_capi.hip", "kernels_stencil2d.hip", "kernels_stencil2d_march.hip", "kernels_stencil3d.hip", "kernels_csr.hip",
-            "kernels_serve.hip", "kernels_apply.hip", "stream_probe.hip")]
+            "kernels_serve.hip", "kernels_apply.hip", "kernels_weights.hip", "stream_probe.hip")]
 BUILD_DIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [

@@ -10,6 +10,7 @@ const void* kernels_stencil2d(bool mixed, int pb, bool group, bool wide);   // w
 const void* kernels_stencil2d_march(bool mixed, int pb);   // row-marching 5-point pass (one-solve kernel)
 const void* kernels_stencil3d(bool mixed, int pb, bool group, bool narrow);   // narrow: IOP windows of 1, 2 (one-solve kernel)
 const void* kernels_csr(bool mixed, int pb, bool group);
+const void* kernels_weights(bool mixed, int pb, bool group);   // per-cell weights stencil
 const void* kernels_serve();   // served form: 2-D and 3-D stencils, FP64 and mixed, p <= 4
 // y = A x in FP64 outside a solve (kernels_apply.hip), enqueued on st
 hipError_t launch_apply(const kiops_operator_desc& d, int64_t N, const double* x, double* y, hipStream_t st);

@@ -74,6 +74,29 @@ __global__ void __launch_bounds__(kApplyThreads) apply_csr_kernel(const int32_t*
   }
 }
 
+// general form: per-cell weights [nw][N] of (centre, +x, -x, +y, -y, +z, -z)
+__global__ void __launch_bounds__(kApplyThreads) apply_weights_kernel(int64_t nx, int64_t ny, int64_t nz, int nw,
+                                                                     const double* __restrict__ W,
+                                                                     const double* __restrict__ x,
+                                                                     double* __restrict__ y, int64_t N) {
+  const int64_t stride = (int64_t)gridDim.x * kApplyThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kApplyThreads + threadIdx.x; i < N; i += stride) {
+    const int64_t ix = i % nx;
+    const int64_t rest = i / nx;
+    const int64_t pos[3] = {ix, rest % ny, rest / ny};
+    const int64_t len[3] = {nx, ny, nz};
+    const int64_t step[3] = {1, nx, nx * ny};
+    double acc = W[i] * x[i];
+    for (int d = 0; 2 * d + 1 < nw; ++d) {
+      const int64_t ip = i + (pos[d] + 1 < len[d] ? step[d] : (1 - len[d]) * step[d]);
+      const int64_t im = i + (pos[d] > 0 ? -step[d] : (len[d] - 1) * step[d]);
+      acc = fma(W[(2 * d + 1) * N + i], x[ip], acc);
+      acc = fma(W[(2 * d + 2) * N + i], x[im], acc);
+    }
+    y[i] = acc;
+  }
+}
+
 int apply_blocks(int64_t n) {
   const int64_t b = (n + kApplyThreads - 1) / kApplyThreads;
   return (int)(b < 65536 ? b : 65536);
@@ -82,7 +105,11 @@ int apply_blocks(int64_t n) {
 }  // namespace
 
 hipError_t launch_apply(const kiops_operator_desc& d, int64_t N, const double* x, double* y, hipStream_t st) {
-  if (d.kind == KIOPS_OP_CSR) {
+  if (d.weights) {
+    const int nw = d.kind == KIOPS_OP_STENCIL2D_5PT ? 5 : 7;
+    hipLaunchKernelGGL(apply_weights_kernel, dim3(apply_blocks(N)), dim3(kApplyThreads), 0, st, (int64_t)d.nx,
+                       (int64_t)d.ny, (int64_t)d.nz, nw, d.weights, x, y, N);
+  } else if (d.kind == KIOPS_OP_CSR) {
     hipLaunchKernelGGL(apply_csr_kernel, dim3(apply_blocks(N)), dim3(kApplyThreads), 0, st, d.rowptr, d.col, d.val,
                        (int64_t)d.nnz, x, y, N);
   } else {

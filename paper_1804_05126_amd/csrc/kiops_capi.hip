@@ -21,6 +21,7 @@
 #include "op_stencil2d_march.h"
 #include "op_stencil3d.h"
 #include "op_csr.h"
+#include "op_weights.h"
 #include "kernel_table.h"
 #include "solver_kernel.h"
 
@@ -73,11 +74,15 @@ struct Layout {
 
 int elem_size(const kiops_operator* op) { return op->d.precision == KIOPS_MIXED ? 4 : 8; }
 
+// Weights per cell of the general stencil form: 5 in 2-D, 7 in 3-D.
+int weight_count(const kiops_operator* op) { return op->d.kind == KIOPS_OP_STENCIL2D_5PT ? 5 : 7; }
+
 // Per-element coefficient streams a pass reads (algorithmic bytes, in units of
 // one basis element): r and kappa for stencils; for CSR the matrix (values and
 // column indices), the row pointers, and U_{k-1} read, U_k written and R_k read
 // again by the product.
 double coef_streams(const kiops_operator* op) {
+  if (op->d.weights) return (double)weight_count(op) + 3.0;   // the weights, and U and R_k as for CSR
   if (op->d.kind == KIOPS_OP_CSR) {
     const double s = (double)elem_size(op);
     return (double)op->d.nnz / (double)op->N * (s + 4.0) / s + 4.0 / s + 3.0;
@@ -90,6 +95,7 @@ double coef_streams(const kiops_operator* op) {
 
 // Elements of T in the mixed-precision coefficient copies.
 size_t coef_copy_elems(const kiops_operator* op) {
+  if (op->d.weights) return (size_t)weight_count(op) * (size_t)op->N;
   if (op->d.kind == KIOPS_OP_CSR) return (size_t)op->d.nnz;
   return (size_t)((op->d.reaction ? 1 : 0) + (op->d.kappa ? 1 : 0)) * (size_t)op->N;
 }
@@ -100,6 +106,7 @@ int p_bucket(int p) { return p == 0 ? 0 : (p <= 2 ? 2 : (p <= 4 ? 4 : 8)); }
 // The 7-point marching pass serves 3-D operators and 2-D ones with a
 // diffusivity field (nz = 1); the 5-point tile pass serves constant-diffusivity 2-D.
 bool uses_3d(const kiops_operator* op) {
+  if (op->d.weights) return false;   // the general form has a pass of its own
   return op->d.kind == KIOPS_OP_STENCIL3D_7PT || (op->d.kind == KIOPS_OP_STENCIL2D_5PT && op->d.kappa);
 }
 
@@ -144,6 +151,7 @@ bool use_march(const kiops_operator* op, int q) {
 
 // The pass a one-solve kernel runs for this operator and window (KIOPS_PASS_*).
 int pass_kind(const kiops_operator* op, int q) {
+  if (op->d.weights) return KIOPS_PASS_WEIGHTS;
   if (uses_3d(op)) return KIOPS_PASS_7PT;
   if (op->d.kind == KIOPS_OP_CSR) return KIOPS_PASS_CSR;
   if (use_march(op, q)) return KIOPS_PASS_MARCH2D;
@@ -157,6 +165,7 @@ int pass_kind(const kiops_operator* op, int q) {
 const void* kernel_for_bucket(const kiops_operator* op, int pb, bool group, bool wide = false, bool march = false,
                               bool narrow = false) {
   const bool mixed = op->d.precision == KIOPS_MIXED;
+  if (op->d.weights) return kernels_weights(mixed, pb, group);
   if (uses_3d(op)) return kernels_stencil3d(mixed, pb, group, narrow);
   if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
     if (march && !group) return kernels_stencil2d_march(mixed, pb);
@@ -175,6 +184,7 @@ const void* kernel_for(const kiops_operator* op, int p, int q) {
 // pass), strips x row chunks (2-D marching pass), row blocks (CSR).
 int64_t work_tiles(const kiops_operator* op, bool march = false) {
   if (march) return march_items(op);
+  if (op->d.weights) return (op->N + kThreads - 1) / kThreads;   // row blocks
   if (uses_3d(op)) {
     using S = Stencil3D<double, 2>;
     const int64_t tx = (op->d.nx + S::TX - 1) / S::TX;
@@ -211,17 +221,17 @@ kiops_status grid_size(const kiops_operator* op, int p, int q, int* nwg) {
   return KIOPS_OK;
 }
 
-// Default m_max: 128 (Section 3.6.2); 32 for the mixed form, whose FP32 basis
-// loses accuracy over long recurrences (measured relative errors at m_max 128 /
-// 64 / 32: 2.6e-4 / 6.7e-6 / 1.6e-6 on the 256^3 constant-coefficient box,
-// 1.8e-4 / 1.8e-4 / 9.9e-7 and 3.2e-5 / 3.2e-5 / 5.6e-6 on small 3-D boxes
-// with tau ||A||_1 of 306 and 101).
 // The error estimate an options block asks for (KIOPS_ESTIMATE_*), or -1 if invalid.
 int resolve_estimate(const kiops_options* o) {
   const int e = o ? o->estimate : KIOPS_ESTIMATE_ONE_TERM;
   return (e >= KIOPS_ESTIMATE_ONE_TERM && e <= KIOPS_ESTIMATE_CORRECTED) ? e : -1;
 }
 
+// Default m_max: 128 (Section 3.6.2); 32 for the mixed form, whose FP32 basis
+// loses accuracy over long recurrences (measured relative errors at m_max 128 /
+// 64 / 32: 2.6e-4 / 6.7e-6 / 1.6e-6 on the 256^3 constant-coefficient box,
+// 1.8e-4 / 1.8e-4 / 9.9e-7 and 3.2e-5 / 3.2e-5 / 5.6e-6 on small 3-D boxes
+// with tau ||A||_1 of 306 and 101).
 void resolve_options(const kiops_operator* op, const kiops_options* o, int* m_min, int* m_max,
                      int* max_sub) {
   const int m_default = op->d.precision == KIOPS_MIXED ? 32 : 128;
@@ -255,7 +265,7 @@ Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
   L.cgsave = take(sizeof(double) * kLdh);
   const size_t es = (size_t)elem_size(op);
   L.slots = take(es * (size_t)(m_max + 1) * (size_t)op->N);
-  L.ubuf = take((q == 0 || op->d.kind == KIOPS_OP_CSR) ? es * (size_t)op->N : 0);
+  L.ubuf = take((q == 0 || op->d.kind == KIOPS_OP_CSR || op->d.weights) ? es * (size_t)op->N : 0);
   L.bcopy = take(op->d.precision == KIOPS_MIXED ? es * (size_t)p * op->N : 0);
   L.coef = take(op->d.precision == KIOPS_MIXED ? es * coef_copy_elems(op) : 0);
   L.total = off;
@@ -401,6 +411,34 @@ CsrOp<T, PB> make_csr(const kiops_operator* op, int p, const double* const* V, c
   return s;
 }
 
+template <typename T, int PB>
+WeightsOp<T, PB> make_weights(const kiops_operator* op, int p, const double* const* V, char* ws,
+                              const Layout& L) {
+  const auto& d = op->d;
+  WeightsOp<T, PB> s{};
+  s.N = op->N;
+  s.nx = (int)d.nx;
+  s.ny = (int)d.ny;
+  s.nz = (int)d.nz;
+  s.nw = weight_count(op);
+  s.p = p;
+  s.ubuf = reinterpret_cast<T*>(ws + L.ubuf);
+  for (int c = 0; c < kPM; ++c) s.B[c] = nullptr;
+  if (d.precision == KIOPS_MIXED) {
+    T* bc = reinterpret_cast<T*>(ws + L.bcopy);
+    for (int c = 0; c < p; ++c) s.B[c] = bc + (size_t)c * op->N;
+    s.w_src = d.weights;
+    s.w_dst = reinterpret_cast<T*>(ws + L.coef);
+    s.W = s.w_dst;
+  } else {
+    for (int c = 0; c < p; ++c) s.B[c] = reinterpret_cast<const T*>(V[p - c]);
+    s.W = reinterpret_cast<const T*>(d.weights);
+    s.w_src = nullptr;
+    s.w_dst = nullptr;
+  }
+  return s;
+}
+
 KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double tau, int p,
                     const double* const* V, double tol, int m_init, int q, int m_min, int m_max,
                     int max_sub, int mode, double* w) {
@@ -445,7 +483,7 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   P.coefc = reinterpret_cast<double*>(ws + L.coefc);
   P.fullc = reinterpret_cast<double*>(ws + L.fullc);
   P.dpart = reinterpret_cast<double*>(ws + L.dpart);
-  P.ubuf = (q == 0 || op->d.kind == KIOPS_OP_CSR) ? ws + L.ubuf : nullptr;
+  P.ubuf = (q == 0 || op->d.kind == KIOPS_OP_CSR || op->d.weights) ? ws + L.ubuf : nullptr;
   P.partials = reinterpret_cast<double*>(ws + L.partials);
   P.expm = reinterpret_cast<double*>(ws + L.expm);
   P.trace = reinterpret_cast<double*>(ws + L.trace);
@@ -475,7 +513,9 @@ kiops_status stage_op_block(const kiops_operator* op, int p, int pb, const doubl
     case 4: mixed ? stage_op(blk, MAKE<float, 4>(op, p, V, ws, L)) : stage_op(blk, MAKE<double, 4>(op, p, V, ws, L)); break; \
     default: mixed ? stage_op(blk, MAKE<float, 8>(op, p, V, ws, L)) : stage_op(blk, MAKE<double, 8>(op, p, V, ws, L)); break; \
   }
-  if (uses_3d(op)) {
+  if (op->d.weights) {
+    KIOPS_STAGE(make_weights)
+  } else if (uses_3d(op)) {
     KIOPS_STAGE(make_stencil3d)
   } else if (op->d.kind == KIOPS_OP_CSR) {
     KIOPS_STAGE(make_csr)
@@ -495,7 +535,7 @@ const void* group_kernel_for(const kiops_operator* op, int pb) { return kernel_f
 
 // Kernel family of an operator: instances of one batch must share it.
 int op_family(const kiops_operator* op) {
-  const int k = uses_3d(op) ? 1 : (op->d.kind == KIOPS_OP_CSR ? 2 : 0);
+  const int k = op->d.weights ? 3 : (uses_3d(op) ? 1 : (op->d.kind == KIOPS_OP_CSR ? 2 : 0));
   return k * 2 + (op->d.precision == KIOPS_MIXED ? 1 : 0);
 }
 
@@ -570,6 +610,8 @@ void fill_stats(const Ctrl& c, int nwg, double clock_hz, kiops_stats* st) {
   st->time_reduce_s = (double)c.t_red / clock_hz;
   st->time_publish_s = (double)c.t_pub / clock_hz;
   st->time_serial_s = (double)c.t_ser / clock_hz;
+  st->clock_start_s = (double)c.t_begin / clock_hz;
+  st->clock_end_s = (double)c.t_end / clock_hz;
 }
 
 kiops_status check_vectors(const kiops_operator* op, int p, const double* const* V, const double* w) {
@@ -1206,7 +1248,12 @@ kiops_status kiops_create_operator(const kiops_operator_desc* desc, void* hip_st
     if (!std::isfinite(d.diff) || !std::isfinite(d.adv[0]) || !std::isfinite(d.adv[1]) ||
         !std::isfinite(d.adv[2]))
       return KIOPS_ERR_INVALID_ARG;
+    // the general form takes the operator from its weights alone
+    if (d.weights && (d.kappa || d.reaction || d.diff != 0.0 || d.adv[0] != 0.0 || d.adv[1] != 0.0 ||
+                      d.adv[2] != 0.0))
+      return KIOPS_ERR_INVALID_ARG;
   } else if (d.kind == KIOPS_OP_CSR) {
+    if (d.weights) return KIOPS_ERR_INVALID_ARG;
     if (d.nrows < 1 || d.nnz < 0 || !d.rowptr || !d.col || (!d.val && d.nnz > 0)) return KIOPS_ERR_INVALID_ARG;
     // 32-bit byte offsets into val and the basis vectors
     if (d.nnz * (int64_t)sizeof(double) >= ((int64_t)1 << 32) || d.nrows >= ((int64_t)1 << 29))

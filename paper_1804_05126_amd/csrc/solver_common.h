@@ -96,6 +96,7 @@ struct Ctrl {
   // the latest normalised vector v_k: <v_k, A~ v_k> and ||A~ v_k||^2 (the
   // two-term and corrected error estimates use them for v_{m+1})
   double est_c, est_u;
+  uint64_t t_begin, t_end;      // clock at the start and at the end of the solve
 };
 
 // Release word and abort flag on separate 128-byte lines: every workgroup

@@ -184,6 +184,8 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
       P.ctrl->t_red = C.t_red;
       P.ctrl->t_pub = C.t_pub;
       P.ctrl->t_ser = C.t_ser;
+      P.ctrl->t_begin = C.t_begin;
+      P.ctrl->t_end = t2;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELAXED, KIOPS_AGENT);
@@ -613,10 +615,11 @@ __device__ __noinline__ void epilogue_setup(const KParams& P, SmallState& S, dou
       nu = ldexp(1.0, -c);
       mu = ldexp(1.0, c);
     }
-    const uint64_t tw = C.t_work, tl = C.t_last;
+    const uint64_t tw = C.t_work, tl = C.t_last, tb = C.t_begin;
     C = Ctrl{};
     C.t_work = tw;
     C.t_last = tl;
+    C.t_begin = tb;
     C.nu = nu; C.mu = mu;
     C.gather_to = -1;
     C.T_now = 0.0; C.T_end = P.T_end; C.tau = P.T_end; C.tol = P.tol;
@@ -1114,6 +1117,7 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
     S.C.t_release_max = S.C.t_release_mean = 0;
     S.C.t_red = S.C.t_pub = S.C.t_ser = 0;
     S.C.t_last = (uint64_t)wall_clock64();
+    S.C.t_begin = S.C.t_last;
   }
 
   setup_phase<Op, T>(P, op, bcopy, lds);
