@@ -46,6 +46,7 @@ struct Stencil3DT {
   static constexpr bool kTwoPhase = false;   // one fused pass per Krylov step
   static constexpr int kWavesPerEU = sizeof(T) == 4 ? 3 : 3;
   static constexpr int kDepth = 3;   // FP32: plane steps whose loads are in flight at a time
+  static constexpr int kSlabRows = 4;   // tile rows of a slab in the item order
 
   struct PlaneLoads {
     T vr[kRegionLoads], vk[kRegionLoads];   // halo-2 plane of R_{kp-1} and kappa
@@ -191,11 +192,18 @@ struct Stencil3DT {
     int start = 0;
     for (int j = 0; j < mine; start += round_size(j), ++j) {
       const int item = i_lo + start + pos;
-      const int tx = item % tiles_x;
-      const int rest = item / tiles_x;
+      // items run through slabs of kSlabRows tile rows: x fastest, then the
+      // slab's rows, then z chunks (the last slab may have fewer rows)
+      const int per_slab = tiles_x * kSlabRows * nchunks;
+      const int nfull = tiles_y / kSlabRows;
+      const int slab = item / per_slab < nfull ? item / per_slab : nfull;
+      const int hs = slab < nfull ? kSlabRows : tiles_y - nfull * kSlabRows;
+      const int rr = item - slab * per_slab;
+      const int tx = rr % tiles_x;
+      const int r2 = rr / tiles_x;
       const int x0 = tx * TX;
-      const int y0 = (rest % tiles_y) * TY;
-      const int zch = rest / tiles_y;
+      const int y0 = (slab * kSlabRows + r2 % hs) * TY;
+      const int zch = r2 / hs;
       const int z0 = (int)((int64_t)nz * zch / nchunks);
       const int z1 = (int)((int64_t)nz * (zch + 1) / nchunks);
 
