@@ -110,11 +110,16 @@ bool uses_3d(const kiops_operator* op) {
   return op->d.kind == KIOPS_OP_STENCIL3D_7PT || (op->d.kind == KIOPS_OP_STENCIL2D_5PT && op->d.kappa);
 }
 
-// z planes per work item of the marching pass (nominal; sizes the grid): 24
-// measured 1.5% faster than 16 and 2% faster than 32 at 256^3 (FP64)
-int zchunk(const kiops_operator* op) { return (int)std::min<int64_t>(24, op->d.nz); }
+// z planes per work item of the marching pass (nominal; sizes the grid).
+// FP64, whose chunks alternate their march direction: 16 (256^3: 7.65 solves/s
+// against 7.48 with 24, 7.27 with 32, 6.97 with 12); the mixed form, marching
+// in one direction: 24 (1.5% faster than 16 and 2% faster than 32, measured
+// in FP64 before the alternation).
+int zchunk(const kiops_operator* op) {
+  return (int)std::min<int64_t>(op->d.precision == KIOPS_MIXED ? 24 : 16, op->d.nz);
+}
 
-// Number of z chunks for a grid of nwg workgroups: about nz / 24, raised (by at
+// Number of z chunks for a grid of nwg workgroups: about nz / zchunk, raised (by at
 // most half) so that the item count is a multiple of the grid when that is
 // reachable, which gives every workgroup the same number of items.
 int zchunks(const kiops_operator* op, int nwg) {
