@@ -39,6 +39,10 @@ struct SmallState {
   double fy[kPM], fky[kPM], fsi, fck;  // full-window step: y_k, K y_k, 1/s_k, <R_k, U_k>
   double red[16];                    // reduced inner products
   int action, jj, again, expired;
+  // Copy of the solve's parameter block: the epilogue's serial steps read
+  // their parameters from LDS rather than from device memory, where each
+  // read after the barrier's acquire is a round trip of about a microsecond.
+  KParams P;
 };
 
 __device__ inline double h_get(const SmallState& S, int i, int k) {
@@ -244,7 +248,8 @@ __device__ inline bool aborted(const KParams& P) {
 }
 
 // out[d] = sum over workgroups of partials[wg][d], d < kDotSlots, in a fixed
-// order (workgroup index, then lanes, then waves).  Loads are issued four rows
+// order (workgroup index within a thread, a fixed tree over the lanes, then
+// waves).  Loads are issued four rows
 // per thread at a time.
 __device__ inline void reduce_partials(const KParams& P, double* out, double* lds, int rows) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -278,11 +283,10 @@ __device__ inline void reduce_partials(const KParams& P, double* out, double* ld
   for (; w < rows; w += kThreads)
 #pragma unroll
     for (int d = 0; d < kDotSlots; ++d) acc[d] += P.partials[(int64_t)w * P.ndot_stride + d];
+  wave_sum(acc);
+  if (lane == 63) {
 #pragma unroll
-  for (int d = 0; d < kDotSlots; ++d) {
-    double v = acc[d];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if (lane == 0) lds[wv * 16 + d] = v;
+    for (int d = 0; d < kDotSlots; ++d) lds[wv * 16 + d] = acc[d];
   }
   __syncthreads();
   if (t < kDotSlots) {
@@ -652,9 +656,14 @@ __device__ inline int step_normalise(const KParams& P, SmallState& S, int k, dou
   Ctrl& C = S.C;
   const int p = C.p;
   const double* red = S.red;
-  const double* yk = C.q == 0 ? P.Y + k * kPM : y_row(S, k);
+  if (C.q == 0) {   // two loops, so that the windowed form reads LDS directly
 #pragma unroll
-  for (int c = 0; c < kPM; ++c) ykr[c] = yk[c];
+    for (int c = 0; c < kPM; ++c) ykr[c] = P.Y[k * kPM + c];
+  } else {
+    const double* yk = y_row(S, k);
+#pragma unroll
+    for (int c = 0; c < kPM; ++c) ykr[c] = yk[c];
+  }
 #pragma unroll
   for (int c = 0; c < kPM; ++c) Ky[c] = (c + 1 < kPM && c + 1 < p) ? ykr[c + 1] : 0.0;   // K y
   double RR = red[kDotRR], UU = red[kDotUU], Ck = red[kDotCk];
@@ -959,7 +968,7 @@ __device__ inline void store_partials(const KParams& P, const DotAcc& acc, doubl
     packed[kDotC + d] = acc.C[d];
   }
   packed[kDotCk] = acc.Ck;
-  block_sum(packed, kDotSlots, lds, P.partials + (int64_t)vblock() * P.ndot_stride);
+  block_sum(packed, lds, P.partials + (int64_t)vblock() * P.ndot_stride);
 }
 
 template <class Op, typename T>
@@ -983,7 +992,7 @@ __device__ inline void setup_phase(const KParams& P, const Op& op, T* bcopy, dou
     }
   }
   op.setup_coefficients(P, gt, gs);
-  block_sum(sums, kDotSlots, lds, P.partials + (int64_t)vblock() * P.ndot_stride);
+  block_sum(sums, lds, P.partials + (int64_t)vblock() * P.ndot_stride);
 }
 
 // Gather w <- sum_i cg[i] R_i (R_1 = w).
@@ -1120,8 +1129,16 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
     S.C.t_begin = S.C.t_last;
   }
 
+  if (vblock() == 0) {   // workgroup 0's copy of the parameter block (ordered by the barrier below)
+    static_assert(sizeof(KParams) % 8 == 0, "parameter block layout");
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(&P);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(&S.P);
+    for (int i = threadIdx.x; i < (int)(sizeof(KParams) / 8); i += kThreads) dst[i] = src[i];
+  }
+  const KParams& Pe = S.P;   // the epilogues run on workgroup 0 only
+
   setup_phase<Op, T>(P, op, bcopy, lds);
-  grid_barrier(P, S, epoch, [&] { epilogue_setup(P, S, lds); });
+  grid_barrier(P, S, epoch, [&] { epilogue_setup(Pe, S, lds); });
 
   for (;;) {
     // the abort flag, the next phase and (in case it is a pass) the pass
@@ -1148,15 +1165,15 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
         op.pass(pctx, bp, P.w, Rout, acc, reinterpret_cast<T*>(lds));
       }
       store_partials(P, acc, lds);
-      grid_barrier(P, S, epoch, [&] { epilogue_pass(P, S, lds); });
+      grid_barrier(P, S, epoch, [&] { epilogue_pass(Pe, S, lds); });
     } else if (phase == kPhaseDots) {
       dots_phase<T>(P, bp, lds);
-      grid_barrier(P, S, epoch, [&] { epilogue_dots(P, S, lds); });
+      grid_barrier(P, S, epoch, [&] { epilogue_dots(Pe, S, lds); });
     } else if (phase == kPhaseExpm) {
-      expm_phase(P, S, epoch, lds, [&] { epilogue_expm(P, S, lds); });
+      expm_phase(P, S, epoch, lds, [&] { epilogue_expm(Pe, S, lds); });
     } else {
       gather_phase<T>(P, bp, lds);
-      grid_barrier(P, S, epoch, [&] { epilogue_gather(P, S, lds); });
+      grid_barrier(P, S, epoch, [&] { epilogue_gather(Pe, S, lds); });
     }
   }
 }
