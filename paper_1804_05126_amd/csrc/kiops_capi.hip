@@ -43,8 +43,10 @@ struct kiops_server;
 namespace kiops {
 
 // Barrier words and control block before a launch (one workgroup).
-__global__ void kiops_reset_kernel(Barrier* b, Ctrl* c, unsigned* arrive, int nwg, uint64_t* arrive_t) {
+__global__ void kiops_reset_kernel(Barrier* b, Ctrl* c, unsigned* arrive, int nwg, uint64_t* arrive_t,
+                                   uint64_t* tctx) {
   for (int i = threadIdx.x; i < nwg; i += blockDim.x) arrive[i] = 0u;
+  for (int i = threadIdx.x; i < kCtxWords; i += blockDim.x) tctx[i] = 0u;
   for (int i = threadIdx.x; i < 3 * nwg; i += blockDim.x) arrive_t[i] = 0u;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     b->gen = 0;
@@ -67,7 +69,7 @@ constexpr int kGridExpmFrom = 96;   // padded basis size from which the exponent
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t params, ctrl, bar, arrive, arrive_t, H, G, Y, sinv, coefc, fullc, partials, dpart, expm, trace, cgsave,
+  size_t params, ctrl, bar, arrive, arrive_t, tctx, H, G, Y, sinv, coefc, fullc, partials, dpart, expm, trace, cgsave,
       slots, ubuf, bcopy, coef, total;
   int nwg, ndot_stride, q;
 };
@@ -257,6 +259,7 @@ Layout make_layout(const kiops_operator* op, int p, int q, int m_max, int nwg) {
   L.bar = take(sizeof(Barrier));
   L.arrive = take(sizeof(unsigned) * (size_t)nwg);
   L.arrive_t = take(sizeof(uint64_t) * 3 * (size_t)nwg);
+  L.tctx = take(sizeof(uint64_t) * kCtxWords);   // release words: zero before a launch, like the barrier words
   L.H = take(sizeof(double) * kLdh * kLdh);
   L.G = take(sizeof(double) * kLdh * kLdh);
   L.Y = take(sizeof(double) * kLdh * kPM);
@@ -472,6 +475,7 @@ KParams make_params(const kiops_operator* op, const Layout& L, char* ws, double 
   P.bar = reinterpret_cast<Barrier*>(ws + L.bar);
   P.arrive = reinterpret_cast<unsigned*>(ws + L.arrive);
   P.arrive_t = reinterpret_cast<uint64_t*>(ws + L.arrive_t);
+  P.tctx = reinterpret_cast<uint64_t*>(ws + L.tctx);
   const char* ps = std::getenv("KIOPS_POLL_SLEEP");   // experiment override
   P.poll_sleep = ps ? std::max(0, std::min(64, std::atoi(ps))) : 1;
   P.ranks = 1;
@@ -548,7 +552,7 @@ int op_family(const kiops_operator* op) {
 kiops_status run_solve(kiops_operator* op, char* ws, const Layout& L, KParams& P, int p, const double* const* V,
                        Ctrl* host_ctrl, unsigned* host_abort) {
   hipLaunchKernelGGL(kiops_reset_kernel, dim3(1), dim3(256), 0, op->stream, P.bar, P.ctrl, P.arrive, L.nwg,
-                     P.arrive_t);
+                     P.arrive_t, P.tctx);
   if (!hip_ok(hipGetLastError())) return KIOPS_ERR_DEVICE;
   hipError_t e = hipSuccess;
   // parameter block: KParams at +0, operator struct at +2048 (host staging buffer)
@@ -1082,7 +1086,9 @@ kiops_status admit(kiops_server* s, int64_t t, int g0, int k, size_t off, size_t
   Ctrl c{};
   c.phase = kPhaseDone;
   c.status = KIOPS_ERR_DEVICE;
-  if (!hip_ok(hipMemcpyAsync(P.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s->io))) return KIOPS_ERR_DEVICE;
+  if (!hip_ok(hipMemcpyAsync(P.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s->io)) ||
+      !hip_ok(hipMemsetAsync(P.tctx, 0, sizeof(uint64_t) * kCtxWords, s->io)))   // the request's release words
+    return KIOPS_ERR_DEVICE;
   GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->L.queue);
   std::vector<const unsigned char*> ptrs(k);
   std::vector<unsigned> tails(k);

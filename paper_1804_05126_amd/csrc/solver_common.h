@@ -22,6 +22,13 @@ constexpr int kPM = KIOPS_P_MAX;
 constexpr int kWinMax = 4;                          // windows q <= 4 use register accumulators
 constexpr int kTraceMax = 4096;
 constexpr int kTraceStride = 6;
+// Release words of a grid barrier: the next pass's context as 64-bit words
+// that carry the barrier epoch in their high half (phase, kp, flo, dlo, then
+// a, the window coefficients bw[flo..flo+kWinMax) and the trailing parts of
+// the last two vectors, each double as two words).
+constexpr int kCtxUsed = 4 + 2 * (1 + kWinMax + 2 * kPM);
+constexpr int kCtxWords = 64;
+static_assert(kCtxUsed <= kCtxWords, "release words");
 constexpr int kMaxTimes = KIOPS_MAX_TIMES;            // output times of one call
 constexpr int kXcds = 8;                            // accelerator complex dies of an MI355X
 
@@ -150,6 +157,7 @@ struct KParams {
   int task1;                   // Task I: output l is scaled by (1 / T_l)^p (Algorithm 1)
   double times[kMaxTimes];     // T_1 < ... < T_ntimes = T_end
   double* wout[kMaxTimes];     // output l (wout[ntimes - 1] == w, the state)
+  uint64_t* tctx;               // release words (kCtxWords), zero before the launch
 };
 
 // Work queue of one group of workgroups (batched and served launches).  The

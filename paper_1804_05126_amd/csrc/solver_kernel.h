@@ -39,6 +39,7 @@ struct SmallState {
   double fy[kPM], fky[kPM], fsi, fck;  // full-window step: y_k, K y_k, 1/s_k, <R_k, U_k>
   double red[16];                    // reduced inner products
   int action, jj, again, expired;
+  uint32_t ctx_stage[kCtxWords];     // payloads of the release words (every workgroup)
   // Copy of the solve's parameter block: the epilogue's serial steps read
   // their parameters from LDS rather than from device memory, where each
   // read after the barrier's acquire is a round trip of about a microsecond.
@@ -69,39 +70,144 @@ __device__ inline bool spin_expired(Barrier* b, uint64_t t0, uint64_t spin_limit
   return false;
 }
 
+// Payload of release word l (low 32 bits; the epoch is the high half).
+__device__ inline uint32_t ctx_payload(const Ctrl& C, int phase, int l) {
+  if (l == 0) return (uint32_t)phase;
+  if (l == 1) return (uint32_t)C.kp;
+  if (l == 2) return (uint32_t)C.flo;
+  if (l == 3) return (uint32_t)C.dlo;
+  const int d = (l - 4) >> 1;
+  double v;
+  if (d == 0) {
+    v = C.a;
+  } else if (d <= kWinMax) {
+    const int i = C.flo + d - 1;
+    v = i < kLdh ? C.bw[i] : 0.0;
+  } else if (d <= kWinMax + kPM) {
+    v = C.yb_prev[d - 1 - kWinMax];
+  } else {
+    v = C.yb_cur[d - 1 - kWinMax - kPM];
+  }
+  return (uint32_t)(((l - 4) & 1) ? __double2hiint(v) : __double2loint(v));
+}
+
+// Pass context from a control block (workgroup 0: its own; the others: the
+// published one, for the phases and windows the release words do not carry).
+template <typename T>
+__device__ inline void ctx_from_ctrl(const KParams& P, const Ctrl& C, PassCtx<T>& c) {
+  if (threadIdx.x == 0) {
+    c.kp = C.kp;
+    c.src = C.kp - 1;
+    c.flo = C.flo;
+    c.dlo = C.dlo;
+    c.ngd = C.kp - C.dlo;
+    c.first = (C.kp == 1);
+    c.write_out = !(C.kp == 1 && !P.mixed);
+    c.p = C.p;
+    c.a = (T)C.a;
+    c.store_u = (C.q == 0);
+    c.ranks = P.ranks;
+  }
+  for (int i = threadIdx.x; i < kLdh; i += kThreads) c.bw[i] = (T)C.bw[i];
+  if (threadIdx.x < kPM) {
+    c.ybp[threadIdx.x] = (T)C.yb_prev[threadIdx.x];
+    c.ybc[threadIdx.x] = (T)C.yb_cur[threadIdx.x];
+  }
+}
+
+// Pass context from the payloads of the release words (a pass whose window
+// coefficients bw[flo..kp-1] are among the kWinMax carried).  Only those bw
+// entries are written: the passes read no others.
+template <typename T>
+__device__ inline void ctx_from_words(const KParams& P, const uint32_t* st, PassCtx<T>& c) {
+  auto dbl = [&](int d) { return __hiloint2double((int)st[5 + 2 * d], (int)st[4 + 2 * d]); };
+  const int kp = (int)st[1], flo = (int)st[2], dlo = (int)st[3];
+  const int t = threadIdx.x;
+  if (t == 0) {
+    c.kp = kp;
+    c.src = kp - 1;
+    c.flo = flo;
+    c.dlo = dlo;
+    c.ngd = kp - dlo;
+    c.first = (kp == 1);
+    c.write_out = !(kp == 1 && !P.mixed);
+    c.p = P.p;
+    c.a = (T)dbl(0);
+    c.store_u = (P.q == 0);
+    c.ranks = P.ranks;
+  }
+  if (t < kWinMax && flo + t < kLdh) c.bw[flo + t] = (T)dbl(1 + t);
+  if (t < kPM) {
+    c.ybp[t] = (T)dbl(1 + kWinMax + t);
+    c.ybc[t] = (T)dbl(1 + kWinMax + kPM + t);
+  }
+}
+
 // Grid barrier without contended atomics.  Workgroup w publishes its arrival
 // by storing the barrier epoch into arrive[w]; workgroup 0 waits until every
-// slot holds the epoch, runs `epi`, and releases the grid by storing the epoch
-// into `gen`.  Every wait is bounded by spin_limit ticks of the constant-rate
-// clock; on expiry the abort flag is raised and all workgroups leave.
-template <class F>
-__device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& epoch, F&& epi) {
+// slot holds the epoch, runs `epi`, and releases the grid with the release
+// words: the next phase and, for a windowed pass, its whole context, each
+// 64-bit word tagged with the epoch, so that a workgroup that sees every
+// word tagged has the context in hand (one round trip instead of a release
+// flag followed by reads of the control block).  It also stores the epoch
+// into `gen` (the sub-grid barriers wait on that).  On return s_phase holds
+// the next phase and pctx its pass context.  Every wait is bounded by
+// spin_limit ticks of the constant-rate clock; on expiry the abort flag is
+// raised and all workgroups leave (the next phase reads as done).
+template <typename T, class F>
+__device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& epoch, PassCtx<T>& pctx,
+                                    int& s_phase, F&& epi) {
   Barrier* b = P.bar;
   ++epoch;
-  // The workgroup's stores are ordered before thread 0's agent-scope release
+  // The workgroup's stores are ordered before wave 0's agent-scope release
   // (one L2 write-back per workgroup rather than one per wave).
   __syncthreads();
   if (vblock() != 0) {
-    if (threadIdx.x == 0) {
-      if (P.profile) P.arrive_t[vblock()] = (uint64_t)wall_clock64();
-      // release (the workgroup's stores, ordered before this thread by the
-      // barrier above) then the arrival flag; acquire after the release word.
-      // One-sided fences: a full fence would also invalidate the XCD's L2
-      // under the workgroups still running their pass.
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(&P.arrive[vblock()], epoch, __ATOMIC_RELAXED, KIOPS_AGENT);
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      if (lane == 0) {
+        if (P.profile) P.arrive_t[vblock()] = (uint64_t)wall_clock64();
+        // release (the workgroup's stores, ordered before this wave by the
+        // barrier above) then the arrival flag.  One-sided fences: a full
+        // fence would also invalidate the XCD's L2 under the workgroups
+        // still running their pass.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&P.arrive[vblock()], epoch, __ATOMIC_RELAXED, KIOPS_AGENT);
+      }
+      uint64_t w = 0;
+      int expired = 0;
       const uint64_t t0 = (uint64_t)wall_clock64();
       for (unsigned spins = 1;; ++spins) {
-        if (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, KIOPS_AGENT) == epoch) break;
+        if (lane < kCtxUsed) w = __hip_atomic_load(&P.tctx[lane], __ATOMIC_RELAXED, KIOPS_AGENT);
+        if (__all(lane >= kCtxUsed || (uint32_t)(w >> 32) == epoch)) break;
         for (int z = 0; z < P.poll_sleep; ++z) __builtin_amdgcn_s_sleep(2);
-        if ((spins & 63u) == 0 && spin_expired(b, t0, P.spin_limit)) break;
+        if ((spins & 63u) == 0) {
+          int e = 0;
+          if (lane == 0) e = spin_expired(b, t0, P.spin_limit) ? 1 : 0;
+          if (__builtin_amdgcn_readfirstlane(e)) {
+            expired = 1;
+            break;
+          }
+        }
       }
-      if (P.profile) P.arrive_t[P.nwg + vblock()] = (uint64_t)wall_clock64();
+      if (lane == 0 && P.profile) P.arrive_t[P.nwg + vblock()] = (uint64_t)wall_clock64();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (lane < kCtxWords) S.ctx_stage[lane] = (uint32_t)w;
+      if (lane == 0 && expired) S.ctx_stage[0] = (uint32_t)kPhaseDone;
     }
+    __syncthreads();
+    const int ph = (int)S.ctx_stage[0];
+    const int kp = (int)S.ctx_stage[1], flo = (int)S.ctx_stage[2];
+    if (ph == kPhasePass && P.q != 0 && kp - 1 - flo < kWinMax) {
+      ctx_from_words<T>(P, S.ctx_stage, pctx);
+    } else if (ph != kPhaseDone) {
+      ctx_from_ctrl<T>(P, *P.ctrl, pctx);   // published before the release words
+    }
+    if (threadIdx.x == 0) s_phase = ph;
     __syncthreads();
     return;
   }
+  int expired = 0;
   const uint64_t t0 = (uint64_t)wall_clock64();
   for (unsigned spins = 1;; ++spins) {
     int ok = 1;
@@ -112,7 +218,10 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
     if ((spins & 15u) == 0) {
       if (threadIdx.x == 0) S.expired = spin_expired(b, t0, P.spin_limit) ? 1 : 0;   // thread 0 decides
       __syncthreads();
-      if (S.expired) break;
+      if (S.expired) {
+        expired = 1;
+        break;
+      }
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -167,33 +276,42 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
     __syncthreads();
   }
   epi();
-  __syncthreads();   // the epilogue's stores (control block) before thread 0's release
-  if (threadIdx.x == 0) {
-    const uint64_t t2 = (uint64_t)wall_clock64();
-    Ctrl& C = S.C;
-    C.t_work += t0 - C.t_last;
-    C.t_wait += t1 - t0;
-    C.t_epi += t2 - t1;
-    C.t_last = t2;
-    if (P.profile || C.phase == kPhaseDone) {   // the timers the host reads at the end
-      P.ctrl->t_work = C.t_work;
-      P.ctrl->t_wait = C.t_wait;
-      P.ctrl->t_epi = C.t_epi;
-      P.ctrl->t_expm = C.t_expm;
-      P.ctrl->t_arrive_max = C.t_arrive_max;
-      P.ctrl->t_arrive_mean = C.t_arrive_mean;
-      P.ctrl->t_release_max = C.t_release_max;
-      P.ctrl->t_release_mean = C.t_release_mean;
-      P.ctrl->n_barriers = C.n_barriers;
-      P.ctrl->t_red = C.t_red;
-      P.ctrl->t_pub = C.t_pub;
-      P.ctrl->t_ser = C.t_ser;
-      P.ctrl->t_begin = C.t_begin;
-      P.ctrl->t_end = t2;
+  __syncthreads();   // the epilogue's stores (control block) before wave 0's release
+  const int ph = expired ? (int)kPhaseDone : S.C.phase;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+      const uint64_t t2 = (uint64_t)wall_clock64();
+      Ctrl& C = S.C;
+      C.t_work += t0 - C.t_last;
+      C.t_wait += t1 - t0;
+      C.t_epi += t2 - t1;
+      C.t_last = t2;
+      if (P.profile || C.phase == kPhaseDone) {   // the timers the host reads at the end
+        P.ctrl->t_work = C.t_work;
+        P.ctrl->t_wait = C.t_wait;
+        P.ctrl->t_epi = C.t_epi;
+        P.ctrl->t_expm = C.t_expm;
+        P.ctrl->t_arrive_max = C.t_arrive_max;
+        P.ctrl->t_arrive_mean = C.t_arrive_mean;
+        P.ctrl->t_release_max = C.t_release_max;
+        P.ctrl->t_release_mean = C.t_release_mean;
+        P.ctrl->n_barriers = C.n_barriers;
+        P.ctrl->t_red = C.t_red;
+        P.ctrl->t_pub = C.t_pub;
+        P.ctrl->t_ser = C.t_ser;
+        P.ctrl->t_begin = C.t_begin;
+        P.ctrl->t_end = t2;
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELAXED, KIOPS_AGENT);
+    if (lane < kCtxUsed)
+      __hip_atomic_store(&P.tctx[lane], ((uint64_t)epoch << 32) | ctx_payload(S.C, ph, lane), __ATOMIC_RELAXED,
+                         KIOPS_AGENT);
+    if (lane == 0) __hip_atomic_store(&b->gen, epoch, __ATOMIC_RELAXED, KIOPS_AGENT);
   }
+  if (ph != kPhaseDone) ctx_from_ctrl<T>(P, S.C, pctx);
+  if (threadIdx.x == 0) s_phase = ph;
   __syncthreads();
 }
 
@@ -582,8 +700,9 @@ __device__ __forceinline__ int expm_participants(int n16, int nwg) {
 // A grid-wide small exponential: its stages run on the first workgroups of the
 // grid, separated by barriers among them; the others go straight to the grid
 // barrier that ends the phase.
-template <class F>
-__device__ inline void expm_phase(const KParams& P, SmallState& S, unsigned& epoch, double* lds, F&& epi) {
+template <typename T, class F>
+__device__ inline void expm_phase(const KParams& P, SmallState& S, unsigned& epoch, double* lds, PassCtx<T>& pctx,
+                                  int& s_phase, F&& epi) {
   const Ctrl& C = *P.ctrl;
   const int n = uniform(C.e_j) + 1 + (uniform(C.estimate) != KIOPS_ESTIMATE_ONE_TERM ? 1 : 0);
   const int d = uniform(C.e_d), s = uniform(C.e_s), nst = uniform(C.e_nst);
@@ -597,7 +716,7 @@ __device__ inline void expm_phase(const KParams& P, SmallState& S, unsigned& epo
   } else {
     epoch += (unsigned)(nst - 1);
   }
-  grid_barrier(P, S, epoch, epi);
+  grid_barrier(P, S, epoch, pctx, s_phase, epi);
 }
 
 // Epilogue after the setup phase.
@@ -934,29 +1053,6 @@ __device__ __noinline__ void epilogue_gather(const KParams& P, SmallState& S, do
   publish(P, S);
 }
 
-template <typename T>
-__device__ inline void load_pass_ctx_nosync(const KParams& P, PassCtx<T>& c) {
-  const Ctrl& C = *P.ctrl;
-  if (threadIdx.x == 0) {
-    c.kp = C.kp;
-    c.src = C.kp - 1;
-    c.flo = C.flo;
-    c.dlo = C.dlo;
-    c.ngd = C.kp - C.dlo;
-    c.first = (C.kp == 1);
-    c.write_out = !(C.kp == 1 && !P.mixed);
-    c.p = C.p;
-    c.a = (T)C.a;
-    c.store_u = (C.q == 0);
-    c.ranks = P.ranks;
-  }
-  for (int i = threadIdx.x; i < kLdh; i += kThreads) c.bw[i] = (T)C.bw[i];
-  if (threadIdx.x < kPM) {
-    c.ybp[threadIdx.x] = (T)C.yb_prev[threadIdx.x];
-    c.ybc[threadIdx.x] = (T)C.yb_cur[threadIdx.x];
-  }
-}
-
 // Write the per-workgroup partial inner products of a pass (fixed slots kDot*).
 __device__ inline void store_partials(const KParams& P, const DotAcc& acc, double* lds) {
   double packed[kDotSlots];
@@ -1138,20 +1234,12 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
   const KParams& Pe = S.P;   // the epilogues run on workgroup 0 only
 
   setup_phase<Op, T>(P, op, bcopy, lds);
-  grid_barrier(P, S, epoch, [&] { epilogue_setup(Pe, S, lds); });
+  grid_barrier(P, S, epoch, pctx, s_phase, [&] { epilogue_setup(Pe, S, lds); });
 
   for (;;) {
-    // the abort flag, the next phase and (in case it is a pass) the pass
-    // coefficients are read in one round of loads
-    if (threadIdx.x == 0) {
-      const unsigned ab = __hip_atomic_load(&P.bar->abort, __ATOMIC_RELAXED, KIOPS_AGENT);
-      const int ph = __hip_atomic_load(&P.ctrl->phase, __ATOMIC_RELAXED, KIOPS_AGENT);
-      s_phase = ab ? (int)kPhaseDone : ph;
-    }
-    load_pass_ctx_nosync<T>(P, pctx);
-    __syncthreads();
+    // each grid barrier leaves the next phase in s_phase and, for a pass,
+    // its context in pctx
     const int phase = s_phase;
-    __syncthreads();
     if (phase == kPhaseDone) break;
     if (phase == kPhasePass) {
       DotAcc acc;
@@ -1159,21 +1247,21 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
       T* Rout = bp.get_mut(pctx.kp);
       if constexpr (Op::kTwoPhase) {
         op.form(pctx, bp, P.w, Rout);
-        grid_barrier(P, S, epoch, [] {});     // R_kp complete before the product reads it
+        grid_barrier(P, S, epoch, pctx, s_phase, [] {});   // R_kp complete before the product reads it
         op.matvec(pctx, bp, Rout, acc);
       } else {
         op.pass(pctx, bp, P.w, Rout, acc, reinterpret_cast<T*>(lds));
       }
       store_partials(P, acc, lds);
-      grid_barrier(P, S, epoch, [&] { epilogue_pass(Pe, S, lds); });
+      grid_barrier(P, S, epoch, pctx, s_phase, [&] { epilogue_pass(Pe, S, lds); });
     } else if (phase == kPhaseDots) {
       dots_phase<T>(P, bp, lds);
-      grid_barrier(P, S, epoch, [&] { epilogue_dots(Pe, S, lds); });
+      grid_barrier(P, S, epoch, pctx, s_phase, [&] { epilogue_dots(Pe, S, lds); });
     } else if (phase == kPhaseExpm) {
-      expm_phase(P, S, epoch, lds, [&] { epilogue_expm(Pe, S, lds); });
+      expm_phase(P, S, epoch, lds, pctx, s_phase, [&] { epilogue_expm(Pe, S, lds); });
     } else {
       gather_phase<T>(P, bp, lds);
-      grid_barrier(P, S, epoch, [&] { epilogue_gather(Pe, S, lds); });
+      grid_barrier(P, S, epoch, pctx, s_phase, [&] { epilogue_gather(Pe, S, lds); });
     }
   }
 }
