@@ -46,6 +46,14 @@ struct SmallState {
   KParams P;
 };
 
+// Store to device memory through a global (not flat) address.  The serial
+// epilogue interleaves LDS reads with stores of its diagnostics copies; a
+// flat store counts against both wait counters, so every wait for an LDS
+// read would also wait for the previous stores to complete.
+__device__ __forceinline__ void gstore(double* p, double v) {
+  *(__attribute__((address_space(1))) double*)p = v;
+}
+
 __device__ inline double h_get(const SmallState& S, int i, int k) {
   const int d = i - (k - kWinMax + 1);
   return (d >= 0 && d <= kWinMax) ? S.Hb[k][d] : 0.0;
@@ -53,7 +61,7 @@ __device__ inline double h_get(const SmallState& S, int i, int k) {
 __device__ inline void h_set(SmallState& S, const KParams& P, int i, int k, double v) {
   const int d = i - (k - kWinMax + 1);
   if (d >= 0 && d <= kWinMax) S.Hb[k][d] = v;   // the band kept in LDS
-  P.H[i * kLdh + k] = v;                        // full copy in device memory
+  gstore(&P.H[i * kLdh + k], v);                // full copy in device memory
 }
 __device__ inline double g_get(const SmallState& S, int i, int l) {   // |i - l| < kWinMax
   if (i < l) { const int t = i; i = l; l = t; }
@@ -439,7 +447,7 @@ __device__ inline void start_substep(const KParams& P, SmallState& S) {
   for (int c = 0; c < kPM; ++c) {
     C.yb_cur[c] = (c < p) ? C.nu * y1[c] : 0.0;
     C.yb_prev[c] = 0.0;
-    P.Y[1 * kPM + c] = y1[c];
+    gstore(&P.Y[1 * kPM + c], y1[c]);
   }
   C.kp = 1;
   C.flo = 1;
@@ -817,7 +825,7 @@ __device__ inline int step_normalise(const KParams& P, SmallState& S, int k, dou
   C.s_last = s;
   const double si = 1.0 / s;
   S.sinv[k] = si;
-  P.sinv[k] = si;
+  gstore(&P.sinv[k], si);
   S.unorm_prev = sqrt(UU) * si;
   C.est_c = Ck * si * si;                     // <v_k, A~ v_k>
   C.est_u = UU * si * si;                     // ||A~ v_k||^2
@@ -906,7 +914,7 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
         if (c < p)
           for (int i = dlo; i <= k; ++i) v -= hk[i - dlo] * S.sinv[i] * y_row(S, i)[c];
         yn[c] = (c < p) ? v : 0.0;
-        P.Y[(k + 1) * kPM + c] = yn[c];
+        gstore(&P.Y[(k + 1) * kPM + c], yn[c]);
         C.yb_prev[c] = (c < p) ? C.nu * ykr[c] : 0.0;
         C.yb_cur[c] = (c < p) ? C.nu * v : 0.0;
       }
