@@ -515,11 +515,11 @@ def bench_small(args, W, K, np, torch):
     loop_s = time.perf_counter() - t0
     outs = [torch.empty(pr.n, dtype=torch.float64, device="cuda") for _ in range(count)]
     probs = [dict(op=op, tau=pr.tau, vectors=vecs, tol=pr.tol, m_init=pr.m_init, q=pr.q, out=o) for o in outs]
-    best, _ = K.batch_tune(probs, candidates=(8, 16, 32))
-    K.phi_batch(probs, group_size=best)
+    best, rows, _ = K.batch_tune_shape(probs, group_sizes=(8, 16, 32), tile_rows=(16, 8, 4))
+    K.phi_batch(probs, group_size=best, tile_rows=rows)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    _, stats, status, plan = K.phi_batch(probs, group_size=best)
+    _, stats, status, plan = K.phi_batch(probs, group_size=best, tile_rows=rows)
     torch.cuda.synchronize()
     batch_s = time.perf_counter() - t1
     ok = all(x["status"] == 0 for x in stats) and all(torch.equal(o, outs[0]) for o in outs[1:])
@@ -528,7 +528,7 @@ def bench_small(args, W, K, np, torch):
         "ms_per_step": batch_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "2-D ADR 32^2 (N=1024), p=2, tau=1e-2, tol 1e-8, q=2, m_init 10; 1000 solves",
-                   "seed": pr.seed, "group_size": best},
+                   "seed": pr.seed, "group_size": best, "tile_rows": rows},
         "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
                      "note": "the 48 KiB working set stays in L2; per-step barriers and epilogues dominate"},
         "single_solve_ms": _lat(lat), "matvecs_per_solve": st["matvecs"],
@@ -541,7 +541,8 @@ def bench_small(args, W, K, np, torch):
 def bench_batch(args, W, K, np, torch):
     """The batched workload: batch-count independent 2-D problems (side log-U[64,512],
     p in 1..4, tau log-U[1e-4,1e-1]) in one persistent launch, against the same
-    problems solved one after another; the group size is autotuned first."""
+    problems solved one after another; the group size and the 2-D tile height
+    are autotuned first."""
     prec = args.precision
     prs = W.cfg4(count=args.batch_count, precision=prec)
     probs = []
@@ -550,14 +551,15 @@ def bench_batch(args, W, K, np, torch):
         probs.append(dict(op=op, tau=pr.tau, vectors=[torch.as_tensor(v, device="cuda") for v in pr.vectors],
                           tol=pr.tol, m_init=pr.m_init, q=args.q))
     print("[bench] inputs ready", file=sys.stderr, flush=True)
-    best, tune_ms = K.batch_tune(probs, candidates=(8, 16, 32, 64))
-    print(f"[bench] tuned group size {best}", file=sys.stderr, flush=True)
+    gcands, rcands = (8, 16, 32, 64), (16, 8, 4)
+    best, rows, tune_ms = K.batch_tune_shape(probs, group_sizes=gcands, tile_rows=rcands)
+    print(f"[bench] tuned group size {best}, tiles of 64 x {rows}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        K.phi_batch(probs, group_size=best)
+        K.phi_batch(probs, group_size=best, tile_rows=rows)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        outs, stats, status, plan = K.phi_batch(probs, group_size=best)
+        outs, stats, status, plan = K.phi_batch(probs, group_size=best, tile_rows=rows)
         print(f"[bench] batch step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -585,16 +587,18 @@ def bench_batch(args, W, K, np, torch):
         "dtype": "f64" if prec == "fp64" else "f32-basis/f64-accumulate", "data": "synthetic",
         "config": {"workload": (f"batch of {len(probs)} 2-D ADR problems, side log-U[64,512], eps~U[1e-3,1e-1], "
                                 f"alpha~U[-20,20], r~U[-1,0], p~U{{1..4}}, tau~log-U[1e-4,1e-1], tol {prs[0].tol:g}"),
-                   "precision": prec, "seed": prs[0].seed, "group_size": best, "groups": plan[0]},
+                   "precision": prec, "seed": prs[0].seed, "group_size": best, "tile_rows": rows,
+                   "groups": plan[0]},
         "roofline": {"bound": "hbm", "achieved": alg / (wall / args.steps) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": alg / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "kiops_group_kernel<Stencil2D>"},
+                     "kernel": f"kiops_group_kernel<Stencil2D> (64 x {rows} tiles)"},
         "per_solve_loop": {"solves_per_s": len(probs) / loop_wall, **_lat(lat)},
         "batch_latency_ms": wall * 1e3 / args.steps,
         "completion_ms": {"batched": _lat(batch_done), "one_by_one": _lat(loop_done),
                           "note": "all problems submitted at t = 0; batched from the device clock, one by one "
                                   "as the running sum of per-solve times (host clock)"},
-        "autotune": {"candidates": [8, 16, 32, 64], "best_group_size": best, "best_ms": tune_ms},
+        "autotune": {"group_sizes": list(gcands), "tile_rows": list(rcands), "best_group_size": best,
+                     "best_tile_rows": rows, "best_ms": tune_ms},
         "statuses_ok": all(st["status"] == 0 for st in stats),
     }
     print(json.dumps(out), flush=True)

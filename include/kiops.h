@@ -99,12 +99,19 @@ typedef struct {
  * 10 and 128, Section 3.6.2; m_max defaults to 32 for KIOPS_MIXED operators,
  * whose FP32 basis loses accuracy over longer recurrences) and a cap on
  * substeps (default 100000).  A zero field takes its default.  m_max must not
- * exceed KIOPS_M_MAX_LIMIT. */
+ * exceed KIOPS_M_MAX_LIMIT.
+ * tile_rows: rows of the 64-column tiles of the 2-D 5-point tile pass in the
+ * batched form (kiops_batch_plan, kiops_phi_batch, kiops_batch_tune): 16
+ * (0 = default), 8 or 4; other values are INVALID_ARG there.  Shorter tiles
+ * give small grids more work items per group, taller ones re-read fewer halo
+ * rows; kiops_batch_tune_shape picks it.  Single solves and other operator
+ * kinds do not use it. */
 typedef struct {
   int32_t m_min;
   int32_t m_max;
   int32_t max_substeps;
   int32_t estimate;   /* KIOPS_ESTIMATE_*: the error estimate of an attempt (Section 3.4) */
+  int32_t tile_rows;  /* batched 2-D tile pass: 16 (0), 8 or 4 */
 } kiops_options;
 
 /* kiops_options.estimate.  Every variant takes its terms from the expansion
@@ -298,13 +305,28 @@ kiops_status kiops_phi_batch(int count, const kiops_problem* probs, const kiops_
                              int group_size, void* workspace, size_t workspace_bytes, void* hip_stream,
                              kiops_stats* stats);
 
-/* Autotuner of the batched form: runs the batch once per candidate group size
- * (candidates: host array, n entries; each the group_size of kiops_phi_batch)
- * and returns the fastest in *best and its time in *best_ms.  The workspace
+/* Autotuner of the batched form: times the batch for each candidate group
+ * size (the better of two runs; candidates: host array, n entries; each the
+ * group_size of kiops_phi_batch) and returns the fastest in *best and its time
+ * in *best_ms.  The workspace
  * must hold the largest plan among the candidates.  Outputs w are written. */
 kiops_status kiops_batch_tune(int count, const kiops_problem* probs, const kiops_options* opts,
                               const int* candidates, int n, void* workspace, size_t workspace_bytes,
                               void* hip_stream, int* best, double* best_ms);
+
+/* Autotuner over batch shapes: times the batch (the better of two runs) for
+ * each pair (group_sizes[i], tile_rows[j]) (host arrays of ng and nt entries;
+ * each tile_rows 16, 8 or 4, used as kiops_options.tile_rows, the other
+ * fields from opts) and returns the fastest pair in *best_group_size, *best_tile_rows and its time in
+ * *best_ms.  Operator kinds other than the 2-D 5-point stencil have one tile
+ * shape: their candidates differ in group size only.  The workspace must hold
+ * the largest plan among the candidates (kiops_batch_plan for each).  Outputs
+ * w are written.  Errors as kiops_phi_batch; INVALID_ARG for empty or
+ * invalid candidate lists. */
+kiops_status kiops_batch_tune_shape(int count, const kiops_problem* probs, const kiops_options* opts,
+                                    const int* group_sizes, int ng, const int* tile_rows, int nt,
+                                    void* workspace, size_t workspace_bytes, void* hip_stream,
+                                    int* best_group_size, int* best_tile_rows, double* best_ms);
 
 /*
  * Served form (continuous batching): one long-lived launch whose workgroups

@@ -266,17 +266,18 @@ def _batch_workspace(nbytes: int):
 
 
 def phi_batch(problems: Sequence[dict], group_size: int = 0, m_min: int = 0, m_max: int = 0,
-              max_substeps: int = 0, stream=None):
+              max_substeps: int = 0, stream=None, tile_rows: int = 0):
     """Batched form: every problem (a dict with op, tau, vectors and optionally
     tol, m_init, q, out) solved in one persistent launch.  Returns
     (list of w, list of stats dicts, status, plan) with plan = (groups,
     group_size): the number of groups and the size of the shared groups (a
     problem with a large share of the work runs on a larger group of its own;
-    stats[i]["grid_blocks"] is the size of the group that solved problem i)."""
+    stats[i]["grid_blocks"] is the size of the group that solved problem i).
+    tile_rows: rows of the 2-D tile pass's tiles (16 (0), 8 or 4)."""
     torch = _torch()
     lib = _lib.load()
     arr, keep, outs = _batch_problems(problems)
-    o = _lib.Options(m_min, m_max, max_substeps, 0)
+    o = _lib.Options(m_min, m_max, max_substeps, 0, int(tile_rows))
     nbytes, groups, gs = C.c_size_t(), C.c_int(), C.c_int()
     _lib.check(lib.kiops_batch_plan(len(problems), arr, C.byref(o), int(group_size), C.byref(nbytes),
                                     C.byref(groups), C.byref(gs)), "kiops_batch_plan")
@@ -289,12 +290,12 @@ def phi_batch(problems: Sequence[dict], group_size: int = 0, m_min: int = 0, m_m
 
 
 def batch_tune(problems: Sequence[dict], candidates=(8, 16, 32, 64), m_min: int = 0, m_max: int = 0,
-               stream=None):
+               stream=None, tile_rows: int = 0):
     """Autotuner of the batched form: the fastest group size among candidates and its time (ms)."""
     torch = _torch()
     lib = _lib.load()
     arr, keep, outs = _batch_problems(problems)
-    o = _lib.Options(m_min, m_max, 0, 0)
+    o = _lib.Options(m_min, m_max, 0, 0, int(tile_rows))
     need = 0
     for c in candidates:
         nbytes, groups, gs = C.c_size_t(), C.c_int(), C.c_int()
@@ -309,6 +310,34 @@ def batch_tune(problems: Sequence[dict], candidates=(8, 16, 32, 64), m_min: int 
                                     C.c_void_p(s.cuda_stream), C.byref(best), C.byref(best_ms)),
                "kiops_batch_tune")
     return best.value, best_ms.value
+
+
+def batch_tune_shape(problems: Sequence[dict], group_sizes=(8, 16, 32, 64), tile_rows=(16, 8, 4),
+                     m_min: int = 0, m_max: int = 0, stream=None):
+    """Autotuner over batch shapes: the fastest (group size, tile rows) pair
+    among the candidates and its time (ms)."""
+    torch = _torch()
+    lib = _lib.load()
+    arr, keep, outs = _batch_problems(problems)
+    need = 0
+    for r in tile_rows:
+        o = _lib.Options(m_min, m_max, 0, 0, int(r))
+        for c in group_sizes:
+            nbytes, groups, gs = C.c_size_t(), C.c_int(), C.c_int()
+            _lib.check(lib.kiops_batch_plan(len(problems), arr, C.byref(o), int(c), C.byref(nbytes),
+                                            C.byref(groups), C.byref(gs)), "kiops_batch_plan")
+            need = max(need, nbytes.value)
+    ws, wsb = _batch_workspace(need)
+    o = _lib.Options(m_min, m_max, 0, 0, 0)
+    gcand = (C.c_int * len(group_sizes))(*group_sizes)
+    rcand = (C.c_int * len(tile_rows))(*tile_rows)
+    bg, br, bms = C.c_int(), C.c_int(), C.c_double()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _lib.check(lib.kiops_batch_tune_shape(len(problems), arr, C.byref(o), gcand, len(group_sizes), rcand,
+                                          len(tile_rows), C.c_void_p(ws), wsb, C.c_void_p(s.cuda_stream),
+                                          C.byref(bg), C.byref(br), C.byref(bms)),
+               "kiops_batch_tune_shape")
+    return bg.value, br.value, bms.value
 
 
 class Server:

@@ -53,7 +53,7 @@ class OperatorDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("m_min", C.c_int32), ("m_max", C.c_int32), ("max_substeps", C.c_int32),
-                ("estimate", C.c_int32)]
+                ("estimate", C.c_int32), ("tile_rows", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -135,6 +135,10 @@ SIGNATURES = [
     ("kiops_batch_tune", C.c_int, [C.c_int, C.POINTER(Problem), C.POINTER(Options), C.POINTER(C.c_int),
                                    C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_int),
                                    C.POINTER(C.c_double)]),
+    ("kiops_batch_tune_shape", C.c_int, [C.c_int, C.POINTER(Problem), C.POINTER(Options), C.POINTER(C.c_int),
+                                         C.c_int, C.POINTER(C.c_int), C.c_int, C.c_void_p, C.c_size_t,
+                                         C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                         C.POINTER(C.c_double)]),
     ("kiops_server_fixed_bytes", C.c_int, [C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_int)]),
     ("kiops_server_create", C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_void_p)]),

@@ -6,7 +6,8 @@
 
 namespace kiops {
 
-const void* kernels_stencil2d(bool mixed, int pb, bool group, bool wide);   // wide: IOP windows of 3, 4 (one-solve kernel)
+// wide: IOP windows of 3, 4 (one-solve kernel); tile_rows: 16, 8 or 4 (group kernel)
+const void* kernels_stencil2d(bool mixed, int pb, bool group, bool wide, int tile_rows = 16);
 const void* kernels_stencil2d_march(bool mixed, int pb);   // row-marching 5-point pass (one-solve kernel)
 const void* kernels_stencil3d(bool mixed, int pb, bool group, bool narrow);   // narrow: IOP windows of 1, 2 (one-solve kernel)
 const void* kernels_csr(bool mixed, int pb, bool group);
@@ -27,6 +28,16 @@ const void* pick_kernel(bool mixed, int pb, bool group) {
     default: return mixed ? KIOPS_K(float, 8) : KIOPS_K(double, 8);
   }
 #undef KIOPS_K
+}
+// the group kernel only
+template <template <typename, int> class OP>
+const void* pick_group_kernel(bool mixed, int pb) {
+  switch (pb) {
+    case 0: return mixed ? (const void*)kiops_group_kernel<OP<float, 0>, float> : (const void*)kiops_group_kernel<OP<double, 0>, double>;
+    case 2: return mixed ? (const void*)kiops_group_kernel<OP<float, 2>, float> : (const void*)kiops_group_kernel<OP<double, 2>, double>;
+    case 4: return mixed ? (const void*)kiops_group_kernel<OP<float, 4>, float> : (const void*)kiops_group_kernel<OP<double, 4>, double>;
+    default: return mixed ? (const void*)kiops_group_kernel<OP<float, 8>, float> : (const void*)kiops_group_kernel<OP<double, 8>, double>;
+  }
 }
 // the one-solve kernel only
 template <template <typename, int> class OP>

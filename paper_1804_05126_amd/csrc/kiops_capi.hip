@@ -170,13 +170,13 @@ int pass_kind(const kiops_operator* op, int q) {
 // march: the row-marching 5-point one-solve kernel; narrow: the 7-point
 // one-solve kernel for IOP windows of 1 and 2.
 const void* kernel_for_bucket(const kiops_operator* op, int pb, bool group, bool wide = false, bool march = false,
-                              bool narrow = false) {
+                              bool narrow = false, int tile_rows = 16) {
   const bool mixed = op->d.precision == KIOPS_MIXED;
   if (op->d.weights) return kernels_weights(mixed, pb, group);
   if (uses_3d(op)) return kernels_stencil3d(mixed, pb, group, narrow);
   if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
     if (march && !group) return kernels_stencil2d_march(mixed, pb);
-    return kernels_stencil2d(mixed, pb, group, wide);
+    return kernels_stencil2d(mixed, pb, group, wide, tile_rows);
   }
   if (op->d.kind == KIOPS_OP_CSR) return kernels_csr(mixed, pb, group);
   return nullptr;
@@ -187,9 +187,9 @@ const void* kernel_for(const kiops_operator* op, int p, int q) {
   return kernel_for_bucket(op, p_bucket(p), false, q == 3 || q == 4, use_march(op, q), q == 1 || q == 2);
 }
 
-// Work items of the pass: tiles (2-D tile pass), columns x z chunks (7-point
-// pass), strips x row chunks (2-D marching pass), row blocks (CSR).
-int64_t work_tiles(const kiops_operator* op, bool march = false) {
+// Work items of the pass: tiles (2-D tile pass, 64 x tile_rows), columns x z
+// chunks (7-point pass), strips x row chunks (2-D marching pass), row blocks (CSR).
+int64_t work_tiles(const kiops_operator* op, bool march = false, int tile_rows = 16) {
   if (march) return march_items(op);
   if (op->d.weights) return (op->N + kThreads - 1) / kThreads;   // row blocks
   if (uses_3d(op)) {
@@ -201,7 +201,7 @@ int64_t work_tiles(const kiops_operator* op, bool march = false) {
   }
   if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
     const int64_t tx = (op->d.nx + Stencil2D<double, 2>::TX - 1) / Stencil2D<double, 2>::TX;
-    const int64_t ty = (op->d.ny + Stencil2D<double, 2>::TY - 1) / Stencil2D<double, 2>::TY;
+    const int64_t ty = (op->d.ny + tile_rows - 1) / tile_rows;
     return tx * ty;
   }
   if (op->d.kind == KIOPS_OP_CSR) return (op->N + kThreads - 1) / kThreads;   // row blocks
@@ -291,16 +291,17 @@ bool hip_ok(hipError_t e) {
   return false;
 }
 
-template <typename T, int PB>
-Stencil2D<T, PB> make_stencil2d(const kiops_operator* op, int p, const double* const* V, char* ws,
-                                const Layout& L) {
+template <typename T, int PB, int kTY = 16>
+Stencil2DT<T, PB, false, kTY> make_stencil2d(const kiops_operator* op, int p, const double* const* V, char* ws,
+                                             const Layout& L) {
+  using S2 = Stencil2DT<T, PB, false, kTY>;
   const auto& d = op->d;
-  Stencil2D<T, PB> s{};
+  S2 s{};
   s.N = op->N;
   s.nx = (int)d.nx;
   s.ny = (int)d.ny;
-  s.tiles_x = (int)((d.nx + Stencil2D<T, PB>::TX - 1) / Stencil2D<T, PB>::TX);
-  const int tiles_y = (int)((d.ny + Stencil2D<T, PB>::TY - 1) / Stencil2D<T, PB>::TY);
+  s.tiles_x = (int)((d.nx + S2::TX - 1) / S2::TX);
+  const int tiles_y = (int)((d.ny + S2::TY - 1) / S2::TY);
   s.ntiles = s.tiles_x * tiles_y;
   const double cD = d.diff / (d.h * d.h);
   const double cx = d.adv[0] / (2.0 * d.h);
@@ -327,6 +328,17 @@ Stencil2D<T, PB> make_stencil2d(const kiops_operator* op, int p, const double* c
     s.r_dst = nullptr;
   }
   return s;
+}
+
+template <typename T, int PB>
+Stencil2DRows8<T, PB> make_stencil2d_rows8(const kiops_operator* op, int p, const double* const* V, char* ws,
+                                           const Layout& L) {
+  return make_stencil2d<T, PB, 8>(op, p, V, ws, L);
+}
+template <typename T, int PB>
+Stencil2DRows4<T, PB> make_stencil2d_rows4(const kiops_operator* op, int p, const double* const* V, char* ws,
+                                           const Layout& L) {
+  return make_stencil2d<T, PB, 4>(op, p, V, ws, L);
 }
 
 template <typename T, int PB>
@@ -513,7 +525,7 @@ void stage_op(unsigned char* host_block, const OpT& o) {
 // Write the operator struct of the kernel instantiation for p-bucket pb
 // (pb >= p) into blk + 2048.
 kiops_status stage_op_block(const kiops_operator* op, int p, int pb, const double* const* V, char* ws,
-                            const Layout& L, unsigned char* blk, bool march = false) {
+                            const Layout& L, unsigned char* blk, bool march = false, int tile_rows = 16) {
   const bool mixed = op->d.precision == KIOPS_MIXED;
 #define KIOPS_STAGE(MAKE)                                                                          \
   switch (pb) {                                                                                    \
@@ -530,6 +542,10 @@ kiops_status stage_op_block(const kiops_operator* op, int p, int pb, const doubl
     KIOPS_STAGE(make_csr)
   } else if (op->d.kind == KIOPS_OP_STENCIL2D_5PT && march) {
     KIOPS_STAGE(make_stencil2d_march)
+  } else if (op->d.kind == KIOPS_OP_STENCIL2D_5PT && tile_rows == 8) {
+    KIOPS_STAGE(make_stencil2d_rows8)
+  } else if (op->d.kind == KIOPS_OP_STENCIL2D_5PT && tile_rows == 4) {
+    KIOPS_STAGE(make_stencil2d_rows4)
   } else if (op->d.kind == KIOPS_OP_STENCIL2D_5PT) {
     KIOPS_STAGE(make_stencil2d)
   } else {
@@ -539,8 +555,18 @@ kiops_status stage_op_block(const kiops_operator* op, int p, int pb, const doubl
   return KIOPS_OK;
 }
 
-// Group-kernel instantiation (batched and served forms) for p-bucket pb.
-const void* group_kernel_for(const kiops_operator* op, int pb) { return kernel_for_bucket(op, pb, true); }
+// Group-kernel instantiation (batched and served forms) for p-bucket pb and,
+// for the 2-D tile pass, tiles of tile_rows rows.
+const void* group_kernel_for(const kiops_operator* op, int pb, int tile_rows = 16) {
+  return kernel_for_bucket(op, pb, true, false, false, false, tile_rows);
+}
+
+// kiops_options.tile_rows of the batched form: 16 (0), 8 or 4; -1 if invalid.
+int resolve_tile_rows(const kiops_options* o) {
+  const int r = o ? o->tile_rows : 0;
+  if (r == 0) return 16;
+  return (r == 16 || r == 8 || r == 4) ? r : -1;
+}
 
 // Kernel family of an operator: instances of one batch must share it.
 int op_family(const kiops_operator* op) {
@@ -687,6 +713,7 @@ __global__ void small_expm_kernel(const double* Hs, int n, double tau, double* F
 
 struct BatchPlan {
   int gs = 0, ng = 0, pb = 0, m_min = 0, m_max = 0, max_sub = 0;
+  int tile_rows = 16;                   // 2-D tile pass: rows per tile
   int nwg = 0;                          // workgroups of the launch
   const void* fn = nullptr;
   std::vector<int> gsize, wg0;          // per group: workgroups and the first of them
@@ -731,8 +758,10 @@ kiops_status plan_batch(int count, const kiops_problem* probs, const kiops_optio
   resolve_options(probs[0].op, opts, &B.m_min, &B.m_max, &B.max_sub);
   if (B.m_max > KIOPS_M_MAX_LIMIT || B.m_min > B.m_max || B.m_min < 1) return KIOPS_ERR_INVALID_ARG;
   if (resolve_estimate(opts) != KIOPS_ESTIMATE_ONE_TERM) return KIOPS_ERR_UNSUPPORTED;
+  B.tile_rows = resolve_tile_rows(opts);
+  if (B.tile_rows < 0) return KIOPS_ERR_INVALID_ARG;
   B.pb = p_bucket(pmax);
-  B.fn = group_kernel_for(probs[0].op, B.pb);
+  B.fn = group_kernel_for(probs[0].op, B.pb, B.tile_rows);
   if (!B.fn) return KIOPS_ERR_UNSUPPORTED;
   int per_cu = 0;
   if (!hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, B.fn, kThreads, 0)) || per_cu < 1)
@@ -742,7 +771,7 @@ kiops_status plan_batch(int count, const kiops_problem* probs, const kiops_optio
   if (gs <= 0) {
     // about a quarter of the median problem's work tiles, a power of two in [8, 64]
     std::vector<int64_t> tiles(count);
-    for (int i = 0; i < count; ++i) tiles[i] = work_tiles(probs[i].op);
+    for (int i = 0; i < count; ++i) tiles[i] = work_tiles(probs[i].op, false, B.tile_rows);
     std::nth_element(tiles.begin(), tiles.begin() + count / 2, tiles.end());
     const int64_t want = std::max<int64_t>(1, tiles[count / 2] / 4);
     gs = 8;
@@ -772,7 +801,7 @@ kiops_status plan_batch(int count, const kiops_problem* probs, const kiops_optio
       if ((int)dedicated.size() + 1 >= count) break;   // keep one problem for the shared groups
       int want = gs;   // the power of two nearest (in ratio) to its share of the workgroups
       while (want < budget && 1.5 * (double)want < (double)total * est[i] / tot) want *= 2;
-      want = std::min(want, std::max(gs, pow2_floor(std::max<int64_t>(1, work_tiles(probs[i].op)))));
+      want = std::min(want, std::max(gs, pow2_floor(std::max<int64_t>(1, work_tiles(probs[i].op, false, B.tile_rows)))));
       while (want > gs && used + want > budget) want /= 2;
       if (want <= gs) break;             // sorted: every later problem wants less
       dedicated.push_back(i);
@@ -864,7 +893,7 @@ kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B
       P.ctrl = reinterpret_cast<Ctrl*>(ws + B.ctrl_off + ctrl_stride() * i);
       unsigned char* blk = blocks.data() + (size_t)4096 * i;
       std::memcpy(blk, &P, sizeof(KParams));
-      kiops_status s = stage_op_block(pr.op, pr.p, B.pb, pr.V, base, L, blk);
+      kiops_status s = stage_op_block(pr.op, pr.p, B.pb, pr.V, base, L, blk, false, B.tile_rows);
       if (s != KIOPS_OK) return s;
       Q.blocks[e] = reinterpret_cast<const unsigned char*>(ws + B.block_off + (size_t)4096 * i);
     }
@@ -1477,6 +1506,24 @@ kiops_status kiops_phi_batch(int count, const kiops_problem* probs, const kiops_
                    stats, nullptr);
 }
 
+namespace {
+// One autotuner measurement: the better of two runs of the plan (the first
+// launch of a kernel instantiation also pays for loading its code).
+kiops_status tune_run(int count, const kiops_problem* probs, const BatchPlan& B, void* workspace, void* hip_stream,
+                      double* ms) {
+  double best = 0.0;
+  for (int r = 0; r < 2; ++r) {
+    double t = 0.0;
+    kiops_status s = run_batch(count, probs, B, reinterpret_cast<char*>(workspace),
+                               reinterpret_cast<hipStream_t>(hip_stream), nullptr, &t);
+    if (s != KIOPS_OK) return s;
+    best = (r == 0 || t < best) ? t : best;
+  }
+  *ms = best;
+  return KIOPS_OK;
+}
+}  // namespace
+
 kiops_status kiops_batch_tune(int count, const kiops_problem* probs, const kiops_options* opts,
                               const int* candidates, int n, void* workspace, size_t workspace_bytes,
                               void* hip_stream, int* best, double* best_ms) {
@@ -1490,12 +1537,47 @@ kiops_status kiops_batch_tune(int count, const kiops_problem* probs, const kiops
     if (s != KIOPS_OK) return s;
     if (workspace_bytes < B.total) return KIOPS_ERR_OUT_OF_MEMORY;
     double ms = 0.0;
-    s = run_batch(count, probs, B, reinterpret_cast<char*>(workspace), reinterpret_cast<hipStream_t>(hip_stream),
-                  nullptr, &ms);
+    s = tune_run(count, probs, B, workspace, hip_stream, &ms);
     if (s != KIOPS_OK) return s;
     if (bgs == 0 || ms < bms) { bms = ms; bgs = B.gs; }
   }
   *best = bgs;
+  if (best_ms) *best_ms = bms;
+  return KIOPS_OK;
+}
+
+kiops_status kiops_batch_tune_shape(int count, const kiops_problem* probs, const kiops_options* opts,
+                                    const int* group_sizes, int ng, const int* tile_rows, int nt,
+                                    void* workspace, size_t workspace_bytes, void* hip_stream,
+                                    int* best_group_size, int* best_tile_rows, double* best_ms) {
+  if (!group_sizes || ng < 1 || !tile_rows || nt < 1 || !best_group_size || !best_tile_rows)
+    return KIOPS_ERR_INVALID_ARG;
+  if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return KIOPS_ERR_INVALID_ARG;
+  if (count < 1 || !probs || !probs[0].op) return KIOPS_ERR_INVALID_ARG;
+  kiops_options o = opts ? *opts : kiops_options{};
+  for (int j = 0; j < nt; ++j) {
+    o.tile_rows = tile_rows[j];
+    if (resolve_tile_rows(&o) < 0) return KIOPS_ERR_INVALID_ARG;
+  }
+  // one tile shape for the other operator kinds
+  const bool shaped = probs[0].op->d.kind == KIOPS_OP_STENCIL2D_5PT && !probs[0].op->d.weights;
+  double bms = 0.0;
+  int bgs = 0, brows = 0;
+  for (int j = 0; j < (shaped ? nt : 1); ++j) {
+    o.tile_rows = shaped ? tile_rows[j] : 0;
+    for (int i = 0; i < ng; ++i) {
+      BatchPlan B;
+      kiops_status s = plan_batch(count, probs, &o, group_sizes[i], B);
+      if (s != KIOPS_OK) return s;
+      if (workspace_bytes < B.total) return KIOPS_ERR_OUT_OF_MEMORY;
+      double ms = 0.0;
+      s = tune_run(count, probs, B, workspace, hip_stream, &ms);
+      if (s != KIOPS_OK) return s;
+      if (bgs == 0 || ms < bms) { bms = ms; bgs = B.gs; brows = B.tile_rows; }
+    }
+  }
+  *best_group_size = bgs;
+  *best_tile_rows = brows;
   if (best_ms) *best_ms = bms;
   return KIOPS_OK;
 }

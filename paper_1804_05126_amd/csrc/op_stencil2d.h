@@ -30,15 +30,20 @@ namespace kiops {
 // other arrays, and reuses them and R_{kp-2} for the window's inner products;
 // a separate kernel, so that the common window of 2 keeps its own register
 // allocation (the same code in one kernel cost q = 2 2%, measured).
-template <typename T, int PB, bool kWide>
+// kTY: rows of a tile (16, 8 or 4; the batched form takes the height its
+// autotuner picks: shorter tiles give small grids more work items, taller ones
+// re-read fewer halo rows).  Each wave covers kTY / 4 rows of 64 columns.
+template <typename T, int PB, bool kWide, int kTY = 16>
 struct Stencil2DT {
-  static constexpr int TX = 64, TY = 16;
+  static constexpr int TX = 64, TY = kTY;
+  static_assert(kTY == 4 || kTY == 8 || kTY == 16, "tile rows");
+  static constexpr int kRW = kTY / 4;              // tile rows per wave (positions per thread)
   static constexpr int RX = TX + 4, RY = TY + 4;   // halo-2 region (R_{kp-1})
   static constexpr int SX = TX + 2, SY = TY + 2;   // halo-1 region (R_kp)
   static constexpr int kRingPos = SX * SY - TX * TY;  // halo-1 positions outside the tile
   static constexpr int kRegion = RX * RY;
   static constexpr int kRegionLoads = (kRegion + kThreads - 1) / kThreads;
-  static constexpr int kPos = 5;                   // 4 tile positions + 1 ring position
+  static constexpr int kPos = kRW + 1;             // kRW tile positions + 1 ring position
   static constexpr int kLdsT = RX * RY + SX * SY;  // elements of T
   static constexpr int kLdsDoubles = (int)((kLdsT * sizeof(T) + 7) / 8);
   static constexpr bool kTwoPhase = false;   // one fused pass per Krylov step
@@ -80,7 +85,7 @@ struct Stencil2DT {
     T* sX = lds + RX * RY;
     const int t = threadIdx.x;
     const int cx = t & (TX - 1);
-    const int rg = (t >> 6) * 4;
+    const int rg = (t >> 6) * kRW;
     const bool first = c.first != 0;
     const uint64_t nb = (uint64_t)N * sizeof(T);
     const bool has_old = !first && c.flo < c.src;          // R_{kp-2} in the window
@@ -101,9 +106,9 @@ struct Stencil2DT {
     for (int k = 0; k < PB; ++k) rsB[k] = make_rsrc(k < c.p ? B[k] : nullptr, nb);
     int prx[kPos], pry[kPos];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { prx[i] = cx; pry[i] = rg + i; }
+    for (int i = 0; i < kRW; ++i) { prx[i] = cx; pry[i] = rg + i; }
     const bool ring = t < kRingPos;
-    ring_pos(ring ? t : 0, prx[4], pry[4]);
+    ring_pos(ring ? t : 0, prx[kRW], pry[kRW]);
 
     // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
     // workgroup b runs on XCD b % 8.  Each XCD takes one contiguous band of the
@@ -138,9 +143,9 @@ struct Stencil2DT {
         const int gx = wrap_index(x0 + prx[q], nx);
         const int gy = wrap_index(y0 + pry[q], ny);
         const uint32_t idx = (uint32_t)(gy * nx + gx);
-        goff[q] = (q < 4 || ring) ? idx * (uint32_t)sizeof(T) : kNoOffset;
+        goff[q] = (q < kRW || ring) ? idx * (uint32_t)sizeof(T) : kNoOffset;
         rv[q] = buf_ld(rsr, goff[q], T(0));
-        if (first) ov[q] = (T)buf_ld(rsW, (q < 4 || ring) ? idx * 8u : kNoOffset, 0.0);
+        if (first) ov[q] = (T)buf_ld(rsW, (q < kRW || ring) ? idx * 8u : kNoOffset, 0.0);
         else ov[q] = buf_ld(rsO, goff[q], T(0));
 #pragma unroll
         for (int k = 0; k < PB; ++k) bv[q][k] = buf_ld(rsB[k], goff[q], T(0));
@@ -163,17 +168,17 @@ struct Stencil2DT {
       }
       __syncthreads();
       // ---- form R_kp on the halo-1 region
-      T bcur[4];
+      T bcur[kRW];
 #pragma unroll
       for (int q = 0; q < kPos; ++q) {
-        if (q < 4 || ring) {
+        if (q < kRW || ring) {
           T bprev = T(0), bc = T(0);
 #pragma unroll
           for (int k = 0; k < PB; ++k) {
             bprev = fma(bv[q][k], c.ybp[k], bprev);
             bc = fma(bv[q][k], c.ybc[k], bc);
           }
-          if (q < 4) bcur[q] = bc;
+          if (q < kRW) bcur[q] = bc;
           T X;
           if (first) {
             X = ov[q];
@@ -214,7 +219,7 @@ struct Stencil2DT {
       __syncthreads();
       // ---- U_kp on the tile, output and inner products
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < kRW; ++i) {
         const int ry = rg + i;
         const bool valid = (x0 + cx < nx) && (y0 + ry < ny);
         const int o = (ry + 1) * SX + (cx + 1);
@@ -260,5 +265,9 @@ template <typename T, int PB>
 using Stencil2D = Stencil2DT<T, PB, false>;
 template <typename T, int PB>
 using Stencil2DWide = Stencil2DT<T, PB, true>;
+template <typename T, int PB>
+using Stencil2DRows8 = Stencil2DT<T, PB, false, 8>;   // batched form: 64 x 8 tiles
+template <typename T, int PB>
+using Stencil2DRows4 = Stencil2DT<T, PB, false, 4>;   // batched form: 64 x 4 tiles
 
 }  // namespace kiops

@@ -163,3 +163,60 @@ def test_batch_reports_start_and_end_clocks():
     assert 0.0 < span <= wall
     _, st, _ = K.phi_combination(probs[0]["op"], prs[0].tau, probs[0]["vectors"], tol=prs[0].tol)
     assert st["clock_end_s"] > st["clock_start_s"] > 0.0
+
+
+@pytest.mark.parametrize("tile_rows", [8, 4])
+def test_batch_short_tiles_vs_dense(tile_rows):
+    # the tile heights the shape autotuner may pick: every problem still matches
+    # the dense Theorem-1 result, including sides that are not multiples of the
+    # tile (the problems of cfg4's recipe at 16..64 points a side)
+    import paper_1804_05126_amd as K
+    prs = _small_batch(12, seed=4001)
+    announce(f"batch of 12 2-D problems, 64 x {tile_rows} tiles")
+    for gs in (8, 16):
+        ws, stats, status, plan = K.phi_batch(_problems(prs), group_size=gs, tile_rows=tile_rows)
+        assert status == 0
+        for pr, w, st in zip(prs, ws, stats):
+            assert st["status"] == 0
+            ref = augmented.phi_combination_dense(operators.dense(pr.op), pr.tau, pr.vectors)
+            assert rel(w.cpu().numpy(), ref) <= 1e-8, (pr.name, gs, st)
+
+
+def test_batch_short_tiles_match_single_solves_mixed():
+    import paper_1804_05126_amd as K
+    prs = _small_batch(8, seed=4002, side_range=(40, 120))
+    probs = _problems(prs)
+    announce("batch of 8, 64 x 4 tiles, vs the same problems solved alone")
+    ws, stats, status, plan = K.phi_batch(probs, group_size=8, tile_rows=4)
+    assert status == 0
+    for pr, pb, w in zip(prs, probs, ws):
+        single, st, _ = K.phi_combination(pb["op"], pr.tau, pb["vectors"], tol=pr.tol)
+        assert rel(w.cpu().numpy(), single.cpu().numpy()) <= 1e-8
+    mprs = _small_batch(8, seed=4003, precision="mixed")
+    announce("mixed batch of 8, 64 x 8 tiles")
+    ws, stats, status, plan = K.phi_batch(_problems(mprs, precision="mixed"), group_size=8, tile_rows=8)
+    assert status == 0
+    for pr, w in zip(mprs, ws):
+        ref = augmented.phi_combination_dense(operators.dense(pr.op), pr.tau, pr.vectors)
+        assert rel(w.cpu().numpy(), ref) <= 1e-5
+
+
+def test_batch_tune_shape_picks_a_candidate_pair():
+    import paper_1804_05126_amd as K
+    prs = _small_batch(10, seed=4004)
+    announce("shape autotuner over group sizes (8, 16) and tile rows (16, 8, 4)")
+    gs, rows, ms = K.batch_tune_shape(_problems(prs), group_sizes=(8, 16), tile_rows=(16, 8, 4))
+    assert gs in (8, 16) and rows in (16, 8, 4) and ms > 0.0
+    # 3-D batches have one tile shape: the pair reports the default rows
+    prs3 = [W.diffusion3d_problem(s, 2, 1e-3, seed=4200 + s, tol=1e-8) for s in (8, 10)]
+    gs, rows, ms = K.batch_tune_shape(_problems(prs3), group_sizes=(8,), tile_rows=(4, 8))
+    assert gs == 8 and rows == 16
+
+
+def test_batch_rejects_invalid_tile_rows():
+    import paper_1804_05126_amd as K
+    prs = _small_batch(2, seed=4005)
+    for bad in (5, 32, -4):
+        with pytest.raises(K.KiopsError) as e:
+            K.phi_batch(_problems(prs), group_size=8, tile_rows=bad)
+        assert "INVALID_ARG" in str(e.value)
