@@ -40,6 +40,9 @@ struct SmallState {
   double red[16];                    // reduced inner products
   int action, jj, again, expired;
   uint32_t ctx_stage[kCtxWords];     // payloads of the release words (every workgroup)
+  // next-pass coefficients: the serial step hands them to kPM lanes
+  double nx_si, nx_hk[kWinMax], nx_ky[kPM], nx_ykr[kPM];
+  int nx_k, nx_dlo, nx_p, nx_go;
   // Copy of the solve's parameter block: the epilogue's serial steps read
   // their parameters from LDS rather than from device memory, where each
   // read after the barrier's acquire is a round trip of about a microsecond.
@@ -867,13 +870,14 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
     publish(P, S);
     return;
   }
+  const uint64_t ts0 = P.profile ? (uint64_t)wall_clock64() : 0;
   if (threadIdx.x == 0) {
-    const uint64_t ts0 = P.profile ? (uint64_t)wall_clock64() : 0;
     const int k = C.kp;
     const int dlo = C.dlo;
     const int p = C.p;
     const double* red = S.red;
     double ykr[kPM], Ky[kPM], Ck = 0.0, si = 0.0;
+    S.nx_go = 0;
     int action = step_normalise(P, S, k, ykr, Ky, Ck, si);
     if (action < 0) {
       const int ngd = k - dlo;
@@ -907,26 +911,44 @@ __device__ __noinline__ void epilogue_pass(const KParams& P, SmallState& S, doub
         hk[i - dlo] = h;
         h_set(S, P, i, k, h);
       }
-      // coefficients of the next pass: R_{k+1} = si U_k - sum_i H(i,k) sinv[i] R_i
-      double* yn = y_row(S, k + 1);
+      // coefficients of the next pass: R_{k+1} = si U_k - sum_i H(i,k) sinv[i] R_i;
+      // the y-parts (one entry per lane below) and a, bw here
+      S.nx_si = si;
+      S.nx_k = k;
+      S.nx_dlo = dlo;
+      S.nx_p = p;
+#pragma unroll
+      for (int d = 0; d < kWinMax; ++d) S.nx_hk[d] = d <= k - dlo ? hk[d] : 0.0;
+#pragma unroll
       for (int c = 0; c < kPM; ++c) {
-        double v = (c < p) ? si * Ky[c] : 0.0;
-        if (c < p)
-          for (int i = dlo; i <= k; ++i) v -= hk[i - dlo] * S.sinv[i] * y_row(S, i)[c];
-        yn[c] = (c < p) ? v : 0.0;
-        gstore(&P.Y[(k + 1) * kPM + c], yn[c]);
-        C.yb_prev[c] = (c < p) ? C.nu * ykr[c] : 0.0;
-        C.yb_cur[c] = (c < p) ? C.nu * v : 0.0;
+        S.nx_ky[c] = Ky[c];
+        S.nx_ykr[c] = ykr[c];
       }
+      S.nx_go = 1;
       C.a = si;
       for (int i = dlo; i <= k; ++i) C.bw[i] = -hk[i - dlo] * S.sinv[i];
       action = step_advance(S, k, dlo);
     }
     S.action = action;
     S.jj = k - 1;
-    if (P.profile) C.t_ser += (uint64_t)wall_clock64() - ts0;
   }
   __syncthreads();
+  if (S.nx_go) {   // entry c of the y-parts: the same operations as a loop over c would do
+    const int c = threadIdx.x;
+    if (c < kPM) {
+      const int k = S.nx_k, dlo = S.nx_dlo, p = S.nx_p;
+      double v = (c < p) ? S.nx_si * S.nx_ky[c] : 0.0;
+      if (c < p)
+        for (int i = dlo; i <= k; ++i) v -= S.nx_hk[i - dlo] * S.sinv[i] * y_row(S, i)[c];
+      const double yv = (c < p) ? v : 0.0;
+      y_row(S, k + 1)[c] = yv;
+      gstore(&P.Y[(k + 1) * kPM + c], yv);
+      C.yb_prev[c] = (c < p) ? C.nu * S.nx_ykr[c] : 0.0;
+      C.yb_cur[c] = (c < p) ? C.nu * v : 0.0;
+    }
+    __syncthreads();
+  }
+  if (P.profile && threadIdx.x == 0) C.t_ser += (uint64_t)wall_clock64() - ts0;
   const int action = S.action;
   if (action == 1 || action == 2) attempt_end(P, S, S.jj, action == 2, lds);
   const uint64_t tp0 = P.profile ? (uint64_t)wall_clock64() : 0;
