@@ -35,11 +35,18 @@ __device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, 
 }
 typedef unsigned int kiops_u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
 typedef unsigned int kiops_u32x4 __attribute__((__vector_size__(4 * sizeof(unsigned int))));
+// Stores of pass outputs carry device scope (the sc1 cache-policy bit): they
+// are written through the XCD's L2 instead of staying there dirty, so the
+// agent-scope release fence of the grid barrier that follows every pass has
+// little left to write back (the arrival fence had taken 3-5 us per
+// workgroup at 2048^2; with these stores the sweep is 1.7% faster).  The
+// fences are unchanged: the policy is a placement hint, not the ordering.
+constexpr int kStoreDeviceScope = 16;
 __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(kiops_u32x2, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(kiops_u32x2, v), r, off, 0, kStoreDeviceScope);
 }
 __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, kStoreDeviceScope);
 }
 // two consecutive doubles (16-byte aligned offset)
 __device__ __forceinline__ void buf_ld2(__amdgpu_buffer_rsrc_t r, uint32_t off, double& x, double& y) {
