@@ -125,7 +125,8 @@ __device__ inline void block_sum(const double (&vals)[kCount], double* lds, doub
   if (t < kCount) {
     double s = 0.0;
     for (int w = 0; w < kThreads / 64; ++w) s += lds[w * 64 + t];
-    out[t] = s;
+    // device scope, like the pass outputs (the pass barrier relies on it)
+    __hip_atomic_store(&out[t], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
 }

@@ -165,11 +165,23 @@ __device__ inline void ctx_from_words(const KParams& P, const uint32_t* st, Pass
 // the next phase and pctx its pass context.  Every wait is bounded by
 // spin_limit ticks of the constant-rate clock; on expiry the abort flag is
 // raised and all workgroups leave (the next phase reads as done).
-template <typename T, class F>
+//
+// kWriteThrough: the barrier that ends a single-phase pass, all of whose
+// stores to device memory are device-scope (write-through: buf_st and the
+// partial sums).  The arrival then does not issue the agent-scope release
+// fence, whose L2 write-back took 2.4 us per workgroup on average (4 us for
+// the last one) at 2048^2 even with write-through outputs; instead every wave
+// waits until its own stores have completed, which for device-scope stores
+// means that they have reached the device's coherence point.  (The fence is
+// implemented on this target as that same wait preceded by the write-back of
+// dirty L2 lines, which such stores do not leave.)  Every other barrier, and
+// the release by workgroup 0, keep the fence.
+template <bool kWriteThrough = false, typename T, class F>
 __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& epoch, PassCtx<T>& pctx,
                                     int& s_phase, F&& epi) {
   Barrier* b = P.bar;
   ++epoch;
+  if constexpr (kWriteThrough) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's stores done
   // The workgroup's stores are ordered before wave 0's agent-scope release
   // (one L2 write-back per workgroup rather than one per wave).
   __syncthreads();
@@ -177,12 +189,19 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
     if (threadIdx.x < 64) {
       const int lane = threadIdx.x;
       if (lane == 0) {
-        if (P.profile) P.arrive_t[vblock()] = (uint64_t)wall_clock64();
-        // release (the workgroup's stores, ordered before this wave by the
-        // barrier above) then the arrival flag.  One-sided fences: a full
-        // fence would also invalidate the XCD's L2 under the workgroups
-        // still running their pass.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if constexpr (kWriteThrough) {
+          if (P.profile) {
+            __hip_atomic_store(&P.arrive_t[vblock()], (uint64_t)wall_clock64(), __ATOMIC_RELAXED, KIOPS_AGENT);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+          }
+        } else {
+          if (P.profile) P.arrive_t[vblock()] = (uint64_t)wall_clock64();
+          // release (the workgroup's stores, ordered before this wave by the
+          // barrier above) then the arrival flag.  One-sided fences: a full
+          // fence would also invalidate the XCD's L2 under the workgroups
+          // still running their pass.
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        }
         __hip_atomic_store(&P.arrive[vblock()], epoch, __ATOMIC_RELAXED, KIOPS_AGENT);
       }
       uint64_t w = 0;
@@ -1283,7 +1302,7 @@ __device__ inline void solve_instance(const KParams& P, const Op& op, SmallState
         op.pass(pctx, bp, P.w, Rout, acc, reinterpret_cast<T*>(lds));
       }
       store_partials(P, acc, lds);
-      grid_barrier(P, S, epoch, pctx, s_phase, [&] { epilogue_pass(Pe, S, lds); });
+      grid_barrier<!Op::kTwoPhase>(P, S, epoch, pctx, s_phase, [&] { epilogue_pass(Pe, S, lds); });
     } else if (phase == kPhaseDots) {
       dots_phase<T>(P, bp, lds);
       grid_barrier(P, S, epoch, pctx, s_phase, [&] { epilogue_dots(Pe, S, lds); });
