@@ -334,7 +334,13 @@ __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& e
         P.ctrl->t_end = t2;
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // After a write-through pass barrier whose next phase is a windowed pass,
+    // the other workgroups read only the release words and the pass outputs
+    // (complete, device-scope); workgroup 0's plain stores of this epilogue
+    // (control block, diagnostics) are read by itself or the host alone, so
+    // the release needs no L2 write-back.  Every other release keeps it.
+    const bool words_only = kWriteThrough && ph == kPhasePass && P.q != 0 && S.C.kp - 1 - S.C.flo < kWinMax;
+    if (!words_only) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (lane < kCtxUsed)
       __hip_atomic_store(&P.tctx[lane], ((uint64_t)epoch << 32) | ctx_payload(S.C, ph, lane), __ATOMIC_RELAXED,
                          KIOPS_AGENT);
