@@ -174,8 +174,10 @@ __device__ inline void ctx_from_words(const KParams& P, const uint32_t* st, Pass
 // waits until its own stores have completed, which for device-scope stores
 // means that they have reached the device's coherence point.  (The fence is
 // implemented on this target as that same wait preceded by the write-back of
-// dirty L2 lines, which such stores do not leave.)  Every other barrier, and
-// the release by workgroup 0, keep the fence.
+// dirty L2 lines, which such stores do not leave.)  Every other barrier keeps
+// the fence; workgroup 0's release keeps it unless it follows such a barrier
+// and the next phase is a windowed pass (then the release words are all the
+// other workgroups read).
 template <bool kWriteThrough = false, typename T, class F>
 __device__ inline void grid_barrier(const KParams& P, SmallState& S, unsigned& epoch, PassCtx<T>& pctx,
                                     int& s_phase, F&& epi) {
