@@ -59,6 +59,21 @@ def test_null_arguments_rejected_without_device():
     assert lib.kiops_create_operator(ctypes.byref(d), None, ctypes.byref(out)) == 1
     assert lib.kiops_phi_combination(None, 1.0, 0, None, 1e-8, 10, 2, None, None, None) == 1
     assert lib.kiops_destroy_operator(None) == 1
+    # batch shape tuner: empty candidate lists, missing outputs or an unaligned
+    # workspace are refused before any device call
+    gs, rows = (ctypes.c_int * 2)(8, 16), (ctypes.c_int * 1)(16)
+    bg, br, bms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    args = (0, None, None)
+    assert lib.kiops_batch_tune_shape(*args, None, 0, rows, 1, ctypes.c_void_p(256), 1 << 20, None,
+                                      ctypes.byref(bg), ctypes.byref(br), ctypes.byref(bms)) == 1
+    assert lib.kiops_batch_tune_shape(*args, gs, 2, rows, 0, ctypes.c_void_p(256), 1 << 20, None,
+                                      ctypes.byref(bg), ctypes.byref(br), ctypes.byref(bms)) == 1
+    assert lib.kiops_batch_tune_shape(*args, gs, 2, rows, 1, ctypes.c_void_p(256), 1 << 20, None,
+                                      None, ctypes.byref(br), ctypes.byref(bms)) == 1
+    assert lib.kiops_batch_tune_shape(*args, gs, 2, rows, 1, ctypes.c_void_p(100), 1 << 20, None,
+                                      ctypes.byref(bg), ctypes.byref(br), ctypes.byref(bms)) == 1
+    assert lib.kiops_batch_tune_shape(*args, gs, 2, rows, 1, ctypes.c_void_p(256), 1 << 20, None,
+                                      ctypes.byref(bg), ctypes.byref(br), ctypes.byref(bms)) == 1   # no problems
 
 
 def test_grid_size_product_overflow_rejected():
