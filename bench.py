@@ -161,10 +161,7 @@ def main():
     if args.workload == "batch":
         return bench_batch(args, W, K, np, torch)
     if args.workload == "serve":
-        # the library keeps the served launch switched off (an unexplained
-        # device fault in a served run); nothing of it is started here
-        print("bench.py: the served form is switched off in this library", file=sys.stderr)
-        return 2
+        return bench_serve(args, W, K, np, torch)
     if args.workload == "small":
         return bench_small(args, W, K, np, torch)
     if args.workload == "probe":

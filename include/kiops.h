@@ -343,7 +343,10 @@ kiops_status kiops_batch_tune_shape(int count, const kiops_problem* probs, const
  * waiting ones.  The launch holds two workgroups per CU when the kernel fits
  * three times on a CU (else one), so the device keeps room for the copies and
  * small kernels of other streams.  Memory: the caller's workspace holds the
- * per-group state and the pool; the library allocates nothing.  Not
+ * per-group state and the pool; the group queues and parameter blocks, which
+ * the host writes while the launch runs, are a small mailbox of fine-grained
+ * device memory (about 6.3 KB per group) that the library allocates on the
+ * first server of a device and reuses for later ones (it is never freed).  Not
  * thread-safe: one host thread drives a server.  A bounded wait that expires
  * inside the launch (a minute without progress) fails the request with
  * KIOPS_ERR_DEVICE and the server with it: every later call returns
@@ -359,10 +362,8 @@ kiops_status kiops_server_fixed_bytes(int group_size, size_t* bytes, int* groups
 /* Launch the server on run_stream (hipStream_t); io_stream (another stream)
  * carries the uploads and polls.  points_per_workgroup: gang sizing (0 =
  * 8192).  workspace: device, 256-byte aligned, at least the fixed bytes; the
- * remainder is the request pool.
- * Currently switched off: returns KIOPS_ERR_UNSUPPORTED after validating its
- * arguments (a device fault seen in a served run has no explanation yet, so
- * the served launch is not started). */
+ * remainder is the request pool (the whole workspace is cleared here).
+ * OUT_OF_MEMORY if the mailbox cannot be allocated. */
 kiops_status kiops_server_create(int group_size, int64_t points_per_workgroup, void* workspace,
                                  size_t workspace_bytes, void* run_stream, void* io_stream, kiops_server** out);
 

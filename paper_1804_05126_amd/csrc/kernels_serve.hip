@@ -56,7 +56,10 @@ __device__ inline void wait_all_at_least(const unsigned* fin, int n, unsigned va
 }
 
 // Workgroup blockIdx.x belongs to group blockIdx.x / group_size and takes its
-// entries from that group's queue.  A request runs on a gang: the aligned run
+// entries from that group's queue.  The queues and parameter blocks are
+// fine-grained memory the host writes while this launch runs: tails are read
+// with system-scope acquires and done/exited words written with system-scope
+// releases (the host reads them).  A request runs on a gang: the aligned run
 // of groups the host chose for it, whose workgroups [P.wg0, P.wg0 + P.nwg)
 // form the virtual grid of the solve (the host pushes the same parameter
 // block to every group of the gang).  Barrier slots are per workgroup
@@ -75,14 +78,15 @@ kiops_serve_kernel(GroupQueue* __restrict__ queues, unsigned* __restrict__ fin, 
   GroupQueue& Q = queues[g];
   for (unsigned e = 0;; ++e) {
     if (threadIdx.x < 64) {
-      const long long r = wait_entry(Q, e);
+      const long long r = wait_entry<__HIP_MEMORY_SCOPE_SYSTEM>(Q, e);
       if (threadIdx.x == 0) s_entry = r;
     }
     __syncthreads();
     const long long entry = s_entry;
     __syncthreads();
     if (entry < 0) {
-      if (local == 0 && threadIdx.x == 0) __hip_atomic_store(&Q.exited, 1u, __ATOMIC_RELEASE, KIOPS_AGENT);
+      if (local == 0 && threadIdx.x == 0)
+        __hip_atomic_store(&Q.exited, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       return;
     }
     // wave-uniform block pointer: the block's fields go to scalar registers
@@ -113,7 +117,7 @@ kiops_serve_kernel(GroupQueue* __restrict__ queues, unsigned* __restrict__ fin, 
     }
     if (local == 0 && threadIdx.x < 64) {
       wait_all_at_least(fin + (size_t)g * group_size, group_size, e + 1, fin_limit);
-      if (threadIdx.x == 0) __hip_atomic_store(&Q.done, e + 1, __ATOMIC_RELEASE, KIOPS_AGENT);
+      if (threadIdx.x == 0) __hip_atomic_store(&Q.done, e + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
   }
 }

@@ -955,7 +955,7 @@ kiops_status run_batch(int count, const kiops_problem* probs, const BatchPlan& B
 // ---------------------------------------------------------------- server
 
 constexpr int kServePB = 4;   // p-bucket of the served kernel (p <= 4)
-constexpr bool kServedEnabled = false;   // see kiops_server_create
+constexpr bool kServedEnabled = true;   // compile-time switch of kiops_server_create
 
 int serve_family(const kiops_operator* op) {
   const bool mixed = op->d.precision == KIOPS_MIXED;
@@ -985,10 +985,10 @@ kiops_status serve_geometry(int group_size, int* gs_out, int* ng_out) {
 
 // Fixed part of a server workspace, in this order: one Barrier and one
 // control block per group (a gang uses its first group's), the per-workgroup
-// arrival slots, arrival clocks (3 per workgroup) and finish words, the group
-// queues and one parameter block per group.
+// arrival slots, arrival clocks (3 per workgroup) and finish words.  The
+// group queues and parameter blocks are not in the workspace (see Mailbox).
 struct ServeLayout {
-  size_t bar, ctrl, arrive, arrive_t, fin, queue, block, pool;
+  size_t bar, ctrl, arrive, arrive_t, fin, pool;
 };
 ServeLayout serve_layout(int gs, int ng) {
   ServeLayout L{};
@@ -1000,10 +1000,55 @@ ServeLayout serve_layout(int gs, int ng) {
   L.arrive = take(sizeof(unsigned) * nwg);
   L.arrive_t = take(sizeof(uint64_t) * 3 * nwg);
   L.fin = take(sizeof(unsigned) * nwg);
-  L.queue = take(sizeof(GroupQueue) * ng);
-  L.block = take((size_t)4096 * ng);
   L.pool = off;
   return L;
+}
+
+// Mailbox of a server: its group queues, then one 4096-byte parameter block
+// per group.  The host writes both while the served launch runs.  Memory
+// from hipMalloc (the workspace) is coarse-grained: HIP makes host writes to
+// it visible to kernels only at kernel boundaries, so a running kernel could
+// see a queue tail before the block pointer and parameter block it
+// publishes.  The mailbox is fine-grained device memory instead, coherent
+// while kernels run; the served kernel reads the tails with system-scope
+// acquires and writes its done words with system-scope releases.  Mailboxes
+// are taken from a per-process list and given back by kiops_server_destroy,
+// never freed.
+constexpr size_t kMailboxBlock = 4096;
+size_t mailbox_queue_bytes(int ng) { return align_up(sizeof(GroupQueue) * (size_t)ng); }
+size_t mailbox_bytes(int ng) { return mailbox_queue_bytes(ng) + kMailboxBlock * (size_t)ng; }
+
+struct Mailbox {
+  int dev;
+  size_t bytes;
+  char* p;
+};
+std::mutex g_mailbox_mu;
+std::vector<Mailbox> g_mailbox_free;
+
+// A mailbox of at least `bytes` on device dev (current), its size in *got.
+char* mailbox_take(int dev, size_t bytes, size_t* got) {
+  {
+    std::lock_guard<std::mutex> lk(g_mailbox_mu);
+    for (size_t i = 0; i < g_mailbox_free.size(); ++i) {
+      if (g_mailbox_free[i].dev == dev && g_mailbox_free[i].bytes >= bytes) {
+        char* p = g_mailbox_free[i].p;
+        *got = g_mailbox_free[i].bytes;
+        g_mailbox_free.erase(g_mailbox_free.begin() + i);
+        return p;
+      }
+    }
+  }
+  void* p = nullptr;
+  if (!hip_ok(hipExtMallocWithFlags(&p, bytes, hipDeviceMallocFinegrained))) return nullptr;
+  *got = bytes;
+  return static_cast<char*>(p);
+}
+
+void mailbox_give(int dev, size_t bytes, char* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_mailbox_mu);
+  g_mailbox_free.push_back(Mailbox{dev, bytes, p});
 }
 
 }  // namespace
@@ -1020,6 +1065,9 @@ struct kiops_server {
   hipStream_t run = nullptr, io = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  int dev = 0;
+  char* mail = nullptr;                 // group queues, then parameter blocks (fine-grained)
+  size_t mail_bytes = 0;
   int gs = 0, ng = 0, max_gang = 1;
   int64_t gang_points = kGangPointsDefault;
   uint64_t clock_hz = 0;
@@ -1104,8 +1152,12 @@ kiops_status admit(kiops_server* s, int64_t t, int g0, int k, size_t off, size_t
   P.arrive_t = reinterpret_cast<uint64_t*>(s->ws + s->L.arrive_t) + 3 * (size_t)wg0;
   P.family = serve_family(pr.op);
   P.wg0 = wg0;
+  // Epochs start above every epoch any finished request has reached, on any
+  // group: the release words and barrier words a finished request left in
+  // the pool block or the barrier (which this request may reuse) then never
+  // match an epoch of this one, and nothing has to be cleared first.
   unsigned e0 = 0;
-  for (int g = g0; g < g0 + k; ++g) e0 = std::max(e0, s->last_epoch[g]);
+  for (int g = 0; g < s->ng; ++g) e0 = std::max(e0, s->last_epoch[g]);
   P.epoch0 = e0;
   alignas(256) unsigned char blk[4096];
   std::memset(blk, 0, sizeof(blk));
@@ -1115,15 +1167,15 @@ kiops_status admit(kiops_server* s, int64_t t, int g0, int k, size_t off, size_t
   Ctrl c{};
   c.phase = kPhaseDone;
   c.status = KIOPS_ERR_DEVICE;
-  if (!hip_ok(hipMemcpyAsync(P.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s->io)) ||
-      !hip_ok(hipMemsetAsync(P.tctx, 0, sizeof(uint64_t) * kCtxWords, s->io)))   // the request's release words
+  if (!hip_ok(hipMemcpyAsync(P.ctrl, &c, sizeof(Ctrl), hipMemcpyHostToDevice, s->io)))
     return KIOPS_ERR_DEVICE;
-  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->L.queue);
+  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->mail);
   std::vector<const unsigned char*> ptrs(k);
   std::vector<unsigned> tails(k);
   for (int i = 0; i < k; ++i) {
     const int g = g0 + i;
-    unsigned char* dblk = reinterpret_cast<unsigned char*>(s->ws + s->L.block + (size_t)4096 * g);
+    unsigned char* dblk =
+        reinterpret_cast<unsigned char*>(s->mail + mailbox_queue_bytes(s->ng) + kMailboxBlock * g);
     ptrs[i] = dblk;
     tails[i] = s->pushed[g] + 1;
     if (!hip_ok(hipMemcpyAsync(dblk, blk, sizeof(blk), hipMemcpyHostToDevice, s->io)) ||
@@ -1600,8 +1652,6 @@ kiops_status kiops_server_create(int group_size, int64_t points_per_workgroup, v
   if (st != KIOPS_OK) return st;
   const ServeLayout SL = serve_layout(gs, ng);
   if (workspace_bytes <= SL.pool) return KIOPS_ERR_OUT_OF_MEMORY;
-  // The served launch stays off until a device fault seen in a served run is
-  // explained; the code below is kept for that investigation.
   if (!kServedEnabled) return KIOPS_ERR_UNSUPPORTED;
   kiops_server* s = new (std::nothrow) kiops_server();
   if (!s) return KIOPS_ERR_OUT_OF_MEMORY;
@@ -1615,6 +1665,12 @@ kiops_status kiops_server_create(int group_size, int64_t points_per_workgroup, v
   if (points_per_workgroup > 0) s->gang_points = points_per_workgroup;
   int dev = 0, khz = 0;
   hipGetDevice(&dev);
+  s->dev = dev;
+  s->mail = mailbox_take(dev, mailbox_bytes(ng), &s->mail_bytes);
+  if (!s->mail) {
+    delete s;
+    return KIOPS_ERR_OUT_OF_MEMORY;
+  }
   if (!hip_ok(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) || khz <= 0) khz = 100000;
   s->clock_hz = (uint64_t)khz * 1000ull;
   s->L = SL;
@@ -1632,17 +1688,22 @@ kiops_status kiops_server_create(int group_size, int64_t points_per_workgroup, v
     const char* is = std::getenv("KIOPS_IDLE_SLEEP");   // experiment override
     Q.idle_sleep = is ? (unsigned)std::max(0, std::min(64, std::atoi(is))) : 4u;
   }
-  if (!hip_ok(hipMemsetAsync(s->ws, 0, SL.queue, s->io)) ||
-      !hip_ok(hipMemcpyAsync(s->ws + SL.queue, q.data(), sizeof(GroupQueue) * ng, hipMemcpyHostToDevice, s->io)) ||
+  // the whole workspace starts at zero: release words that requests leave in
+  // the pool carry epochs of this server only (see admit)
+  if (!hip_ok(hipMemsetAsync(s->ws, 0, SL.pool + s->pool_bytes, s->io)) ||
+      !hip_ok(hipMemsetAsync(s->mail, 0, s->mail_bytes, s->io)) ||
+      !hip_ok(hipMemcpyAsync(s->mail, q.data(), sizeof(GroupQueue) * ng, hipMemcpyHostToDevice, s->io)) ||
       !hip_ok(hipStreamSynchronize(s->io))) {
+    mailbox_give(s->dev, s->mail_bytes, s->mail);
     delete s;
     return KIOPS_ERR_DEVICE;
   }
-  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + SL.queue);
+  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->mail);
   unsigned* fin = reinterpret_cast<unsigned*>(s->ws + SL.fin);
   uint64_t fin_limit = s->clock_hz * 60ull;
   void* args[] = {&dq, &fin, &s->gs, &fin_limit};
   if (!hip_ok(hipLaunchCooperativeKernel(kernels_serve(), dim3(ng * gs), dim3(kThreads), args, 0, s->run))) {
+    mailbox_give(s->dev, s->mail_bytes, s->mail);
     delete s;
     return KIOPS_ERR_DEVICE;
   }
@@ -1676,7 +1737,7 @@ kiops_status kiops_server_progress(kiops_server* s, int* running, int* waiting) 
   if (s->dead) return KIOPS_ERR_DEVICE;
   // the done and exited words of every group queue
   std::vector<unsigned> words(2 * s->ng, 0);
-  const GroupQueue* dq = reinterpret_cast<const GroupQueue*>(s->ws + s->L.queue);
+  const GroupQueue* dq = reinterpret_cast<const GroupQueue*>(s->mail);
   if (!hip_ok(hipMemcpy2DAsync(words.data(), 2 * sizeof(unsigned), &dq->done, sizeof(GroupQueue),
                                2 * sizeof(unsigned), s->ng, hipMemcpyDeviceToHost, s->io)) ||
       !hip_ok(hipStreamSynchronize(s->io)))
@@ -1769,11 +1830,14 @@ kiops_status kiops_server_result(kiops_server* s, int64_t ticket, int* done, kio
 kiops_status kiops_server_destroy(kiops_server* s) {
   if (!s) return KIOPS_ERR_INVALID_ARG;
   const unsigned one = 1;
-  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->ws + s->L.queue);
+  GroupQueue* dq = reinterpret_cast<GroupQueue*>(s->mail);
   kiops_status st = KIOPS_OK;
   for (int g = 0; g < s->ng; ++g)
     if (!hip_ok(hipMemcpyAsync(&dq[g].closed, &one, sizeof(one), hipMemcpyHostToDevice, s->io))) st = KIOPS_ERR_DEVICE;
   if (!hip_ok(hipStreamSynchronize(s->io)) || !hip_ok(hipStreamSynchronize(s->run))) st = KIOPS_ERR_DEVICE;
+  // the launch has ended (or the device is lost): the mailbox can serve
+  // another server, unless the launch may still be running
+  if (st == KIOPS_OK) mailbox_give(s->dev, s->mail_bytes, s->mail);
   delete s;
   return st;
 }

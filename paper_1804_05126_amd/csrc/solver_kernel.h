@@ -1237,13 +1237,17 @@ __device__ inline void dots_phase(const KParams& P, const BasisPtrs<T>& bp, doub
 // Entry e of a group queue: e once the host has published it, or -1 when the
 // queue is closed (and drained) or nothing came within its idle limit.  Called
 // by the whole first wave with wave-uniform values (one loop exit, one result).
+// kScope is the scope of the tail's acquire: the agent when the queue was
+// filled before the launch, the system when the host fills it while the
+// launch runs (a fine-grained queue).
+template <int kScope = KIOPS_AGENT>
 __device__ inline long long wait_entry(GroupQueue& Q, unsigned e) {
   const uint64_t t0 = (uint64_t)wall_clock64();
   long long result = -2;
   while (result == -2) {
-    const unsigned tail = __builtin_amdgcn_readfirstlane(__hip_atomic_load(&Q.tail, __ATOMIC_ACQUIRE, KIOPS_AGENT));
+    const unsigned tail = __builtin_amdgcn_readfirstlane(__hip_atomic_load(&Q.tail, __ATOMIC_ACQUIRE, kScope));
     const unsigned closed =
-        __builtin_amdgcn_readfirstlane(__hip_atomic_load(&Q.closed, __ATOMIC_RELAXED, KIOPS_AGENT));
+        __builtin_amdgcn_readfirstlane(__hip_atomic_load(&Q.closed, __ATOMIC_RELAXED, kScope));
     const bool idle = (uint64_t)wall_clock64() - t0 > Q.idle_limit;
     if (tail > e) {
       result = e;

@@ -19,14 +19,7 @@ from oracle import augmented, operators
 
 from gpu_helpers import announce, rel, to_dev
 
-pytestmark = [
-    pytest.mark.gpu,
-    # A full GPU-suite run faulted the device inside the first served test
-    # (kiops_server_submit returned a device error right after the launch);
-    # the cause has not been found by reading the code, so the served tests
-    # stay off the GPU until it is.
-    pytest.mark.skip(reason="served form: a device fault in the first served test is not yet explained"),
-]
+pytestmark = pytest.mark.gpu
 
 
 def _requests(count, seed):
