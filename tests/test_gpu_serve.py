@@ -167,3 +167,30 @@ def test_served_bitwise_alone_and_in_mix():
         st, w = res[tickets[i]]
         assert st["grid_blocks"] == alone[i][0]
         assert np.array_equal(w, alone[i][1]), (prs[i].name, rel(w, alone[i][1]))
+
+
+def test_served_first_use_of_every_queue_slot():
+    """Regression test of the request hand-over: many small requests submitted
+    together land on fresh groups, so each is read from a queue slot and a
+    parameter block the launch has never read before (the case in which a
+    launch that saw a tail before its block pointer or block contents read a
+    null or uninitialised pointer).  Two servers in a row, the second on the
+    mailbox the first gave back.  Every result must equal the dense Theorem-1
+    result."""
+    import paper_1804_05126_amd as K
+    prs = [W.adr2d_problem(16 + 4 * (i % 5), 1 + i % 2, 1e-3 * (1 + i % 3), seed=5400 + i)
+           for i in range(40)]
+    ins = _inputs(prs)
+    refs = [augmented.phi_combination_dense(operators.dense(pr.op), pr.tau, pr.vectors) for pr in prs]
+    for rep in range(2):
+        srv = K.Server(pool_bytes=1 << 30, group_size=8)
+        announce(f"served first use (server {rep}): {len(prs)} requests on {srv.groups} groups of 8")
+        try:
+            tickets = [srv.submit(op, pr.tau, vecs, tol=pr.tol) for pr, (op, vecs) in zip(prs, ins)]
+            res = _drain(srv, tickets)
+        finally:
+            srv.close()
+        for pr, ref, t in zip(prs, refs, tickets):
+            st, w = res[t]
+            assert st["status"] == 0, (rep, pr.name)
+            assert rel(w, ref) <= 1e-8, (rep, pr.name, rel(w, ref))
