@@ -340,9 +340,9 @@ kiops_status kiops_batch_tune_shape(int count, const kiops_problem* probs, const
  * waiting request finds no free gang, the gang with the fewest busy groups is
  * reserved for it and at most eight later requests may start elsewhere in the
  * meantime.  kiops_server_progress retires finished requests and admits
- * waiting ones.  The launch holds two workgroups per CU when the kernel fits
- * three times on a CU (else one), so the device keeps room for the copies and
- * small kernels of other streams.  Memory: the caller's workspace holds the
+ * waiting ones.  The launch holds one workgroup fewer per CU than fit there
+ * (one, for the current served kernel), so the device keeps room for the
+ * copies and small kernels of other streams.  Memory: the caller's workspace holds the
  * per-group state and the pool; the group queues and parameter blocks, which
  * the host writes while the launch runs, are a small mailbox of fine-grained
  * device memory (about 6.3 KB per group) that the library allocates on the

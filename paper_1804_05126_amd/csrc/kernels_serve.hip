@@ -69,7 +69,10 @@ __device__ inline void wait_all_at_least(const unsigned* fin, int n, unsigned va
 // done only after all of its workgroups have left the solve (fin), so the
 // host never reuses a parameter block, control block or workspace that a
 // workgroup may still read.
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 8)))
+// Up to 256 VGPRs (two waves per SIMD): the four family bodies spill heavily
+// under a 168-register cap (three waves per SIMD), and the launch holds one
+// workgroup per CU either way, leaving room for another stream's work.
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 kiops_serve_kernel(GroupQueue* __restrict__ queues, unsigned* __restrict__ fin, int group_size,
                    uint64_t fin_limit) {
   __shared__ long long s_entry;

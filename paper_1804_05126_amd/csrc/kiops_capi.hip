@@ -966,9 +966,9 @@ int serve_family(const kiops_operator* op) {
 
 constexpr int64_t kGangPointsDefault = 8192;   // grid points per workgroup when sizing a gang
 
-// Groups of group_size workgroups over `per_cu` workgroups per CU (two when
-// the served kernel fits twice on a CU, leaving a wave slot per SIMD and a
-// third of the LDS to other work, else one).
+// Groups of group_size workgroups over `per_cu` workgroups per CU: one fewer
+// than fit on a CU (at most two, at least one), so that a CU keeps room for a
+// workgroup of other work beside the launch.
 kiops_status serve_geometry(int group_size, int* gs_out, int* ng_out) {
   int dev = 0, cus = 0, fit = 0;
   if (!hip_ok(hipGetDevice(&dev)) ||

@@ -157,7 +157,7 @@ struct KParams {
   int task1;                   // Task I: output l is scaled by (1 / T_l)^p (Algorithm 1)
   double times[kMaxTimes];     // T_1 < ... < T_ntimes = T_end
   double* wout[kMaxTimes];     // output l (wout[ntimes - 1] == w, the state)
-  uint64_t* tctx;               // release words (kCtxWords), zero before the launch
+  uint64_t* tctx;               // release words (kCtxWords): zero, or tagged below this solve's epochs
 };
 
 // Work queue of one group of workgroups (batched and served launches).  The
